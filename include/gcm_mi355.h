@@ -1,0 +1,146 @@
+/*
+ * gcm_mi355.h -- C ABI of the MI355X (gfx950) AES-GCM library.
+ *
+ * The library computes AES-GCM authenticated encryption and decryption with
+ * verification, as fixed by NIST SP 800-38D over FIPS-197 AES (the paper's
+ * "Cryptographic Protocol: AES-GCM" section), with the GHASH recurrence
+ * (the paper's serial equation for Y_i) re-bracketed as a reduction tree over
+ * GF(2^128) ("Parallel GHASH Reduction" section, its tree figure, and the
+ * two-phase map-reduce of "Scalable MapReduce for Massive Files").
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Return value: GCM_OK (0) on success, a negative GCM_E_* code otherwise
+ *    (the paper's API table: 0 success, < 0 system error).  A failed
+ *    authentication is NOT an error: decrypt-verify returns GCM_OK with the
+ *    accept flag 0 and the plaintext output zero-filled (the paper's payload
+ *    suppression in "Policy Enforcement and Granular Access").
+ *  - On an error return nothing has been launched and no output was touched.
+ *    gcm_last_error() returns a thread-local message for the last error.
+ *  - Pointers named *_d are DEVICE pointers on the context's device (for
+ *    example torch.Tensor.data_ptr()); all other pointers are HOST pointers.
+ *    Device payload pointers (aad_d, in, out) must be 16-byte aligned.
+ *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
+ *    it in stream order.
+ *  - Keys are 16, 24 or 32 bytes (AES-128/192/256).  IVs are 12 bytes (the
+ *    paper's 96-bit nonces); J0 = IV || 0^31 || 1 and data block i (0-based)
+ *    uses counter inc32^(i+1)(J0), independent of launch geometry (the
+ *    paper's geometry-agnostic counter mapping).  Tags are 16 bytes.
+ *  - Limits (SP 800-38D): len <= 2^36 - 32 bytes, aad_len < 2^61 bytes,
+ *    else GCM_E_TOOLONG.
+ *  - in == out is allowed (in place); partially overlapping in/out is
+ *    GCM_E_ALIAS.
+ *  - The caller owns every buffer.  The context owns its key table and its
+ *    internal scratch.  No call keeps a caller pointer after it returns.
+ *  - No C++ exception crosses this interface.
+ */
+#ifndef GCM_MI355_H
+#define GCM_MI355_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCM_OK 0
+#define GCM_E_ARG (-1)     /* null pointer, bad size, bad op, misaligned pointer */
+#define GCM_E_KEYLEN (-2)  /* key length not 16, 24 or 32 */
+#define GCM_E_IVLEN (-3)   /* IV length not 12 */
+#define GCM_E_TOOLONG (-4) /* len or aad_len beyond the SP 800-38D limits */
+#define GCM_E_NOMEM (-5)   /* device or pinned allocation failed / budget exceeded */
+#define GCM_E_HIP (-6)     /* a HIP runtime call failed */
+#define GCM_E_BUSY (-7)    /* no free key slot / serving queue full */
+#define GCM_E_ALIAS (-8)   /* in and out overlap without being equal */
+#define GCM_E_SLOT (-9)    /* key slot index not registered */
+
+typedef struct gcm_ctx gcm_ctx;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.
+ *   hbm_budget_bytes: upper bound on device memory the context itself may
+ *     allocate for key slots and scratch (0 = no bound).
+ *   key_slots: number of resident key slots (each holds the round keys, H,
+ *     the H^(2^k) power table and the GHASH multiplication tables, about
+ *     386 KiB; the paper's precomputed table of powers of H).
+ * Builds the AES tables on the device.  *out receives the context. */
+int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_bytes, uint32_t key_slots);
+
+/* Wait for all work of the context, then free everything it owns. */
+int gcm_ctx_destroy(gcm_ctx *ctx);
+
+/* Thread-local message describing the last error on this thread ("" if none). */
+const char *gcm_last_error(void);
+
+/* ---------------------------------------------------------------- keys */
+
+/* Expand `key` into a resident slot on `stream`: AES round keys, H =
+ * AES_K(0^128), H^(2^k) for k = 0..47 and the GHASH tables (the paper's
+ * H-power precompute, done on the GPU).  *slot_out receives the slot index.
+ * The slot is usable by later work on the same stream (or after a sync).
+ * GCM_E_BUSY if every slot is taken. */
+int gcm_key_register(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, void *stream);
+
+/* Return a slot to the free list.  The caller guarantees no queued work
+ * still uses it. */
+int gcm_key_release(gcm_ctx *ctx, uint32_t slot);
+
+/* ---------------------------------------------------------------- one-shot, blocking */
+
+/* AES-GCM authenticated encryption (SP 800-38D GCM-AE).
+ * key, iv: host.  aad_d (aad_len bytes), pt_d (len bytes), ct_d (len bytes): device.
+ * tag_out: host, 16 bytes.  Keys are cached in the context's key table, so a
+ * repeated key costs no re-expansion.  Blocks until the tag is on the host. */
+int gcm_encrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
+                uint8_t tag_out[16], void *stream);
+
+/* AES-GCM authenticated decryption (SP 800-38D GCM-AD) with verification.
+ * tag: host, 16 bytes (expected tag).  *accept (host) receives 1 if the tag
+ * matches (pt_d then holds the plaintext) and 0 otherwise (pt_d is then all
+ * zeros).  Tags are compared over all 16 bytes without early exit.  Blocks
+ * until the flag is on the host. */
+int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                       const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                       const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream);
+
+/* ---------------------------------------------------------------- asynchronous, resident key */
+
+/* Device scratch bytes an asynchronous call on a message of `len` data bytes
+ * and `aad_len` AAD bytes needs (the per-tile partial hashes of the map
+ * phase).  A workspace may be reused by calls that are ordered on one stream. */
+uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
+
+/* Same computation as gcm_encrypt, fully on the device and without host
+ * synchronisation: the key comes from a registered slot, the tag is written
+ * to tag_d (device, 16 bytes).  workspace_d: device scratch of at least
+ * gcm_workspace_size() bytes, 16-byte aligned. */
+int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
+                      uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d, uint8_t *tag_d,
+                      void *workspace_d, uint64_t workspace_bytes, void *stream);
+
+/* Same computation as gcm_decrypt_verify on the device: expected tag read
+ * from tag_d (device), the accept flag written to accept_d (device int32:
+ * 1 accept, 0 reject; on reject pt_d is zero-filled by a later kernel on the
+ * same stream). */
+int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                             const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                             const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
+                             uint64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- tuning */
+
+/* Launch shape of the fused tile kernel.  Results never depend on it (the
+ * counter and GHASH exponents derive from block indices only); only speed
+ * does.  log2_tile_blocks: blocks per wave tile (6..20, 0 = automatic);
+ * waves_per_group: 4, 8 or 16 (0 = automatic); groups_per_cu: resident
+ * workgroups per compute unit (0 = automatic). */
+int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group, uint32_t groups_per_cu);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GCM_MI355_H */

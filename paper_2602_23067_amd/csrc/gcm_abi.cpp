@@ -1,0 +1,482 @@
+// gcm_abi.cpp -- host runtime behind the C ABI in include/gcm_mi355.h:
+// device context, resident key table (with a small cache for the one-shot
+// calls), launch planning and the single-message entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/gcm_mi355.h"
+#include "gcm_host.h"
+
+using namespace gcm;
+
+// ---------------------------------------------------------------- errors
+
+static thread_local std::string g_last_error;
+
+int gcm::fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int gcm::fail_hip(hipError_t e, const char *what)
+{
+    return fail(GCM_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+extern "C" const char *gcm_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------- context
+
+static uint32_t ceil_log2(uint64_t x)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < x)
+        ++l;
+    return l;
+}
+
+int gcm::ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes)
+{
+    if (ctx->budget && ctx->used + bytes > ctx->budget)
+        return fail(GCM_E_NOMEM, "allocation of %llu bytes exceeds the context budget (%llu of %llu used)",
+                    (unsigned long long)bytes, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(GCM_E_NOMEM, "hipMalloc(%llu): %s", (unsigned long long)bytes, hipGetErrorString(e));
+    }
+    ctx->used += bytes;
+    return GCM_OK;
+}
+
+void gcm::ctx_free(gcm_ctx *ctx, void *p, uint64_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        ctx->used -= bytes;
+    }
+}
+
+extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_bytes, uint32_t key_slots)
+{
+    if (!out)
+        return fail(GCM_E_ARG, "gcm_ctx_create: out is NULL");
+    *out = nullptr;
+    if (key_slots == 0 || key_slots > (1u << 20))
+        return fail(GCM_E_ARG, "gcm_ctx_create: key_slots must be in 1..2^20");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev)
+        return fail(GCM_E_ARG, "gcm_ctx_create: device %d out of range (%d devices)", device, ndev);
+    e = hipSetDevice(device);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipSetDevice");
+
+    gcm_ctx *ctx = new (std::nothrow) gcm_ctx();
+    if (!ctx)
+        return fail(GCM_E_NOMEM, "gcm_ctx_create: host allocation failed");
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    ctx->n_slots = key_slots;
+    int cus = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+    ctx->cu_count = cus > 0 ? cus : 1;
+
+    int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), 2 * 256 * sizeof(uint32_t));
+    if (rc == GCM_OK)
+        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_slots), kSlotBytes * key_slots);
+    if (rc == GCM_OK)
+        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_io), 256);
+    if (rc == GCM_OK) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_io), 256, hipHostMallocDefault);
+        if (e != hipSuccess)
+            rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+    }
+    if (rc == GCM_OK) {
+        e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, nullptr);
+        if (e == hipSuccess)
+            e = hipDeviceSynchronize();
+        if (e != hipSuccess)
+            rc = fail_hip(e, "AES table initialisation");
+    }
+    if (rc != GCM_OK) {
+        gcm_ctx_destroy(ctx);
+        return rc;
+    }
+    ctx->slot_used.assign(key_slots, 0);
+    ctx->slot_nr.assign(key_slots, 0);
+    ctx->cache_cap = std::max<uint32_t>(1, std::min<uint32_t>(16, key_slots / 2 ? key_slots / 2 : 1));
+    *out = ctx;
+    return GCM_OK;
+}
+
+extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
+{
+    if (!ctx)
+        return fail(GCM_E_ARG, "gcm_ctx_destroy: NULL context");
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx_free(ctx, ctx->d_tables, 2 * 256 * sizeof(uint32_t));
+    ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
+    ctx_free(ctx, ctx->d_io, 256);
+    ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+    if (ctx->h_io)
+        (void)hipHostFree(ctx->h_io);
+    delete ctx;
+    return GCM_OK;
+}
+
+extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group,
+                              uint32_t groups_per_cu)
+{
+    if (!ctx)
+        return fail(GCM_E_ARG, "gcm_set_launch: NULL context");
+    if (log2_tile_blocks && (log2_tile_blocks < 6 || log2_tile_blocks > 20))
+        return fail(GCM_E_ARG, "gcm_set_launch: log2_tile_blocks must be 0 or 6..20");
+    if (waves_per_group && waves_per_group != 4 && waves_per_group != 8 && waves_per_group != 16)
+        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 4, 8 or 16");
+    if (groups_per_cu > 64)
+        return fail(GCM_E_ARG, "gcm_set_launch: groups_per_cu must be <= 64");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->cfg_log2B = log2_tile_blocks;
+    ctx->cfg_waves = waves_per_group;
+    ctx->cfg_gpc = groups_per_cu;
+    return GCM_OK;
+}
+
+// ---------------------------------------------------------------- keys
+
+int gcm::register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, hipStream_t s)
+{
+    uint32_t slot = ctx->n_slots;
+    for (uint32_t i = 0; i < ctx->n_slots; ++i) {
+        if (!ctx->slot_used[i]) {
+            slot = i;
+            break;
+        }
+    }
+    if (slot == ctx->n_slots)
+        return fail(GCM_E_BUSY, "no free key slot (%u slots)", ctx->n_slots);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = launch_key_setup(key, (uint32_t)key_len, ctx->d_slots + kSlotBytes * slot, ctx->d_tables,
+                             ctx->d_tables + 256, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "key setup launch");
+    ctx->slot_used[slot] = 1;
+    ctx->slot_nr[slot] = (uint32_t)(key_len / 4 + 6);
+    *slot_out = slot;
+    return GCM_OK;
+}
+
+static bool valid_key_len(size_t n) { return n == 16 || n == 24 || n == 32; }
+
+extern "C" int gcm_key_register(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, void *stream)
+{
+    if (!ctx || !key || !slot_out)
+        return fail(GCM_E_ARG, "gcm_key_register: NULL argument");
+    if (!valid_key_len(key_len))
+        return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return register_key_locked(ctx, key, key_len, slot_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int gcm_key_release(gcm_ctx *ctx, uint32_t slot)
+{
+    if (!ctx)
+        return fail(GCM_E_ARG, "gcm_key_release: NULL context");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+    for (auto &kv : ctx->cache)
+        if (kv.second == slot)
+            return fail(GCM_E_ARG, "key slot %u belongs to the one-shot key cache", slot);
+    ctx->slot_used[slot] = 0;
+    return GCM_OK;
+}
+
+// one-shot path: look the key up in the cache, expand it on a miss (LRU eviction
+// among cache-owned slots only; the one-shot calls synchronise before
+// returning, so an evicted slot has no work in flight)
+static int cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot, hipStream_t s)
+{
+    std::string k(reinterpret_cast<const char *>(key), key_len);
+    auto it = ctx->cache.find(k);
+    if (it != ctx->cache.end()) {
+        ctx->lru.remove(k);
+        ctx->lru.push_front(k);
+        *slot = it->second;
+        return GCM_OK;
+    }
+    if (ctx->cache.size() >= ctx->cache_cap && !ctx->lru.empty()) {
+        const std::string victim = ctx->lru.back();
+        ctx->lru.pop_back();
+        ctx->slot_used[ctx->cache[victim]] = 0;
+        ctx->cache.erase(victim);
+    }
+    int rc = register_key_locked(ctx, key, key_len, slot, s);
+    if (rc)
+        return rc;
+    ctx->cache[k] = *slot;
+    ctx->lru.push_front(k);
+    return GCM_OK;
+}
+
+// ---------------------------------------------------------------- planning
+
+void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc)
+{
+    const uint32_t w = ctx->cfg_waves ? ctx->cfg_waves : 8;
+    uint32_t g = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)w);
+    *waves = w;
+    *gpc = g;
+    if (ctx->cfg_log2B) {
+        *log2B = ctx->cfg_log2B;
+        return;
+    }
+    // about two wave tiles per resident wave, at least 4 rows per tile
+    const uint64_t resident = (uint64_t)ctx->cu_count * g * w;
+    uint32_t l = ceil_log2((m + 2 * resident - 1) / (2 * resident));
+    *log2B = std::min<uint32_t>(16, std::max<uint32_t>(8, l));
+}
+
+void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in,
+                    uint64_t out, uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr,
+                    uint32_t log2B, uint32_t waves, uint64_t tile_base)
+{
+    std::memset(d, 0, sizeof *d);
+    d->in = in;
+    d->out = out;
+    d->aad = aad;
+    d->tag = tag;
+    d->ok = ok;
+    d->len = len;
+    d->aad_len = aad_len;
+    d->slot = slot_addr;
+    d->n = (len + 15) / 16;
+    d->na = (aad_len + 15) / 16;
+    d->m = d->na + d->n + 1;
+    const uint64_t B = 1ull << log2B;
+    d->n_tiles = (d->m + B - 1) / B;
+    d->z = d->n_tiles * B - d->m;
+    d->tile_base = tile_base;
+    for (int i = 0; i < 3; ++i)
+        d->iv[i] = (uint32_t)iv[4 * i] | ((uint32_t)iv[4 * i + 1] << 8) | ((uint32_t)iv[4 * i + 2] << 16) |
+                   ((uint32_t)iv[4 * i + 3] << 24);
+    d->op = op;
+    d->log2B = log2B;
+    d->nr = nr;
+    d->groups = (uint32_t)((d->n_tiles + waves - 1) / waves);
+}
+
+int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
+{
+    if (len > kMaxLen || aad_len > kMaxAad)
+        return fail(GCM_E_TOOLONG, "len %llu / aad_len %llu beyond the SP 800-38D limits",
+                    (unsigned long long)len, (unsigned long long)aad_len);
+    if ((len && (!in_d || !out_d)) || (aad_len && !aad_d))
+        return fail(GCM_E_ARG, "NULL device buffer with non-zero length");
+    const uintptr_t a = (uintptr_t)aad_d, i = (uintptr_t)in_d, o = (uintptr_t)out_d;
+    if ((aad_len && (a & 15)) || (len && ((i & 15) || (o & 15))))
+        return fail(GCM_E_ARG, "device buffers must be 16-byte aligned");
+    if (len && i != o && i < o + len && o < i + len)
+        return fail(GCM_E_ALIAS, "input and output overlap without being identical");
+    return GCM_OK;
+}
+
+uint64_t gcm::workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs)
+{
+    const uint64_t counters = ((4 + 4 * n_msgs) + 255) / 256 * 256;
+    return counters + 16 * total_tiles;
+}
+
+// Enqueue the kernels for one message on `s`.
+int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
+{
+    uint32_t *counters = reinterpret_cast<uint32_t *>(ws);
+    uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_bytes_for(0, 1);
+    const uint32_t items = d.groups;
+    const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(items, (uint32_t)ctx->cu_count * gpc));
+    hipError_t e = launch_tiles((int)waves, nullptr, nullptr, items, &d, ctx->d_tables, partials, counters, grid, s);
+    if (e == hipSuccess)
+        e = launch_combine(nullptr, 1, &d, ctx->d_tables, ctx->d_tables + 256, partials, counters, s);
+    if (e == hipSuccess && d.op == 1) {
+        const uint64_t chunks = (d.len / 16 + 255) / 256;
+        const uint32_t zgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 4096));
+        e = launch_zerofill(nullptr, &d, counters, zgrid, s);
+    }
+    if (e != hipSuccess)
+        return fail_hip(e, "kernel launch");
+    return GCM_OK;
+}
+
+static uint32_t slot_nr(size_t key_len) { return (uint32_t)(key_len / 4 + 6); }
+
+extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len)
+{
+    if (!ctx)
+        return 0;
+    uint32_t log2B, waves, gpc;
+    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+    launch_shape(ctx, m, &log2B, &waves, &gpc);
+    const uint64_t T = (m + (1ull << log2B) - 1) >> log2B;
+    return workspace_bytes_for(T, 1);
+}
+
+// ensure the context's one-shot workspace holds `bytes` (caller holds ctx->mu)
+static int ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes)
+{
+    if (ctx->ws_bytes >= bytes)
+        return GCM_OK;
+    ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+    ctx->d_ws = nullptr;
+    ctx->ws_bytes = 0;
+    const uint64_t want = std::max<uint64_t>(bytes, 1ull << 20);
+    int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_ws), want);
+    if (rc)
+        return rc;
+    ctx->ws_bytes = want;
+    return GCM_OK;
+}
+
+// ---------------------------------------------------------------- async entry points
+
+static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                        const uint8_t *aad_d, uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d,
+                        const uint8_t *tag_d, int32_t *ok_d, void *ws, uint64_t ws_bytes, void *stream)
+{
+    if (!ctx || !iv || !tag_d || (op == 1 && !ok_d) || !ws)
+        return fail(GCM_E_ARG, "NULL argument");
+    if (iv_len != 12)
+        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    int rc = check_message(aad_len, len, aad_d, in_d, out_d);
+    if (rc)
+        return rc;
+    if ((uintptr_t)ws & 15)
+        return fail(GCM_E_ARG, "workspace must be 16-byte aligned");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+    uint32_t log2B, waves, gpc;
+    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+    launch_shape(ctx, m, &log2B, &waves, &gpc);
+    MsgDesc d;
+    fill_desc(&d, op, iv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
+              (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), 0, log2B, waves, 0);
+    d.nr = ctx->slot_nr[slot];
+    if (ws_bytes < workspace_bytes_for(d.n_tiles, 1))
+        return fail(GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+                    (unsigned long long)ws_bytes, (unsigned long long)workspace_bytes_for(d.n_tiles, 1));
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipSetDevice");
+    return launch_single(ctx, d, waves, gpc, ws, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
+                                 uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d, uint8_t *tag_d,
+                                 void *workspace_d, uint64_t workspace_bytes, void *stream)
+{
+    return async_common(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
+                        workspace_bytes, stream);
+}
+
+extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                                        const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                                        const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
+                                        uint64_t workspace_bytes, void *stream)
+{
+    return async_common(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
+                        workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------- one-shot entry points
+
+static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                   const uint8_t *aad_d, uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d,
+                   const uint8_t *tag_in, uint8_t *tag_out, int *accept, void *stream)
+{
+    if (!ctx || !key || !iv || (op == 0 && !tag_out) || (op == 1 && (!tag_in || !accept)))
+        return fail(GCM_E_ARG, "NULL argument");
+    if (!valid_key_len(key_len))
+        return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
+    if (iv_len != 12)
+        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    int rc = check_message(aad_len, len, aad_d, in_d, out_d);
+    if (rc)
+        return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipSetDevice");
+    uint32_t log2B, waves, gpc;
+    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+    launch_shape(ctx, m, &log2B, &waves, &gpc);
+    const uint64_t T = (m + (1ull << log2B) - 1) >> log2B;
+    rc = ensure_ws_locked(ctx, workspace_bytes_for(T, 1));
+    if (rc)
+        return rc;
+    uint32_t slot;
+    rc = cached_slot_locked(ctx, key, key_len, &slot, s);
+    if (rc)
+        return rc;
+    uint8_t *d_tag = ctx->d_io;                                 // 16 bytes
+    int32_t *d_ok = reinterpret_cast<int32_t *>(ctx->d_io + 16);  // 4 bytes
+    if (op == 1) {
+        e = hipMemcpyAsync(d_tag, tag_in, 16, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess)
+            return fail_hip(e, "tag upload");
+    }
+    MsgDesc d;
+    fill_desc(&d, op, iv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)d_tag,
+              (uint64_t)d_ok, (uint64_t)(ctx->d_slots + kSlotBytes * slot), slot_nr(key_len), log2B, waves, 0);
+    rc = launch_single(ctx, d, waves, gpc, ctx->d_ws, s);
+    if (rc)
+        return rc;
+    e = hipMemcpyAsync(ctx->h_io, ctx->d_io, 32, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail_hip(e, "result download");
+    if (op == 0) {
+        std::memcpy(tag_out, ctx->h_io, 16);
+    } else {
+        int32_t ok;
+        std::memcpy(&ok, ctx->h_io + 16, 4);
+        *accept = ok == 1 ? 1 : 0;
+    }
+    return GCM_OK;
+}
+
+extern "C" int gcm_encrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                           const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
+                           uint8_t tag_out[16], void *stream)
+{
+    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
+                   stream);
+}
+
+extern "C" int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                                  const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                                  const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream)
+{
+    return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream);
+}

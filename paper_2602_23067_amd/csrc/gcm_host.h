@@ -1,0 +1,70 @@
+// gcm_host.h -- host-side internals shared by the runtime sources.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <list>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "gcm_internal.h"
+
+struct gcm_ctx {
+    int device = 0;
+    int cu_count = 1;
+    uint64_t budget = 0;  // 0 = unbounded
+    uint64_t used = 0;
+    uint32_t *d_tables = nullptr;  // TE0[256] then S-box[256] (as words)
+    uint8_t *d_slots = nullptr;    // n_slots * kSlotBytes
+    uint32_t n_slots = 0;
+    std::vector<uint8_t> slot_used;
+    std::vector<uint32_t> slot_nr;  // AES rounds of each registered slot
+    // one-shot key cache
+    std::unordered_map<std::string, uint32_t> cache;
+    std::list<std::string> lru;
+    uint32_t cache_cap = 1;
+    // one-shot scratch
+    uint8_t *d_ws = nullptr;
+    uint64_t ws_bytes = 0;
+    uint8_t *d_io = nullptr;  // device tag (16 B) + flag (4 B)
+    uint8_t *h_io = nullptr;  // pinned mirror
+    // launch shape overrides (0 = automatic)
+    uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0;
+    std::mutex mu;
+};
+
+namespace gcm {
+
+constexpr uint64_t kMaxLen = (1ull << 36) - 32;  // 2^39 - 256 bits
+constexpr uint64_t kMaxAad = (1ull << 61) - 1;   // < 2^64 bits
+
+int fail(int code, const char *fmt, ...);
+int fail_hip(hipError_t e, const char *what);
+
+int ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes);
+void ctx_free(gcm_ctx *ctx, void *p, uint64_t bytes);
+int register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, hipStream_t s);
+
+void launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc);
+void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in, uint64_t out,
+               uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr, uint32_t log2B,
+               uint32_t waves, uint64_t tile_base);
+int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
+uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
+int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
+
+// kernels (gcm_kernels.hip)
+hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s);
+hipError_t launch_key_setup(const uint8_t *key, uint32_t key_len, uint8_t *slot, const uint32_t *te0,
+                            const uint32_t *sbox, hipStream_t s);
+hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, uint32_t n_items,
+                        const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
+                        hipStream_t s);
+int max_groups_per_cu(int waves);
+hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const uint32_t *te0,
+                          const uint32_t *sbox, const void *partials, uint32_t *counters, hipStream_t s);
+hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
+                           hipStream_t s);
+
+}  // namespace gcm

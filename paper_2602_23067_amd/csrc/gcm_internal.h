@@ -1,0 +1,75 @@
+// gcm_internal.h -- layouts shared by the host runtime and the gfx950 kernels.
+//
+// Byte/bit conventions (NIST SP 800-38D sec. 6.3, FIPS-197 sec. 3):
+//  * A 16-byte block is held as four little-endian dwords in memory order:
+//    byte j sits in dword j/4, bits 8*(j%4)..+7.  AES column c is dword c,
+//    AES row r is byte r of a column.
+//  * A GF(2^128) element is held in the same memory order.  Byte j bit s
+//    (value 1<<s) is the coefficient of x^(8j + 7 - s), so the field's one is
+//    byte 0 = 0x80.  Multiplication by a fixed element M is GF(2)-linear, so
+//    X*M = XOR over byte positions j of TAB_j[X_j] with TAB_j[b] = (b at
+//    position j)*M; the tables already contain the reduction, and the hot
+//    loop never swaps bytes or reverses bits.
+#pragma once
+#include <stdint.h>
+
+namespace gcm {
+
+// ---- key slot (device memory, one per resident key) ----
+constexpr int kMaxNr = 14;
+constexpr int kPowLevels = 48;      // H^(2^k), k = 0..47
+constexpr int kTab4Levels = 40;     // nibble tables for H^(2^k), k = 0..39
+constexpr int kStrideLevel = 6;     // the per-lane Horner multiplier is H^64 = H^(2^6)
+
+struct KeySlotHdr {
+    uint32_t rk[4 * (kMaxNr + 1)];  // round keys, memory-order column words
+    uint32_t nr;                    // 10, 12 or 14
+    uint32_t key_len;
+    uint32_t pad0[2];
+    uint32_t h[4];                  // H = AES_K(0^128)
+    uint32_t hpow[kPowLevels][4];   // H^(2^k)
+};
+
+constexpr uint64_t kSlotHdrBytes = 2048;
+constexpr uint64_t kTab8Bytes = 16ull * 256 * 16;             // byte-position table, 64 KiB
+constexpr uint64_t kTab4Bytes = 32ull * 16 * 16;              // nibble-position table, 8 KiB
+constexpr uint64_t kSlotTab8Off = kSlotHdrBytes;
+constexpr uint64_t kSlotTab4Off = kSlotTab8Off + kTab8Bytes;
+constexpr uint64_t kSlotBytes = kSlotTab4Off + kTab4Levels * kTab4Bytes;
+static_assert(sizeof(KeySlotHdr) <= kSlotHdrBytes, "slot header too large");
+
+// ---- per-message descriptor ----
+// GHASH input X = A || 0-pad || C || 0-pad || L has m = nA + n + 1 blocks.
+// It is left-padded with z zero blocks (GHASH(0^z || X) = GHASH(X)) so that
+// m + z = T * B with B = 2^log2B blocks per wave tile; tile t covers padded
+// positions [t*B, (t+1)*B).
+struct MsgDesc {
+    uint64_t in;       // device address of input payload
+    uint64_t out;      // device address of output payload
+    uint64_t aad;      // device address of AAD
+    uint64_t tag;      // encrypt: where the tag goes; decrypt: expected tag (device)
+    uint64_t ok;       // decrypt: int32 accept flag (device); unused for encrypt
+    uint64_t len;      // payload bytes
+    uint64_t aad_len;  // AAD bytes
+    uint64_t slot;     // device address of the key slot
+    uint64_t n;        // data blocks = ceil(len/16)
+    uint64_t na;       // AAD blocks = ceil(aad_len/16)
+    uint64_t m;        // na + n + 1
+    uint64_t z;        // zero-block left padding
+    uint64_t tile_base;  // first wave tile of this message in the partials array
+    uint64_t n_tiles;    // T
+    uint32_t iv[3];      // IV as memory-order dwords
+    uint32_t op;         // 0 encrypt, 1 decrypt-verify
+    uint32_t log2B;      // wave tile = 2^log2B blocks (>= 6)
+    uint32_t nr;         // AES rounds
+    uint32_t groups;     // workgroup items for this message
+    uint32_t pad;
+};
+
+// One unit of work for a workgroup: `waves` consecutive wave tiles of one message.
+struct WorkItem {
+    uint32_t msg;
+    uint32_t first_tile;  // first wave tile (message-local)
+};
+
+}  // namespace gcm

@@ -1,0 +1,734 @@
+// gcm_kernels.hip -- AES-GCM kernels for CDNA4 (gfx950, wave64).
+//
+// Pipeline for one message (the paper's GPU pipeline: H-power generation,
+// AES-CTR, GHASH map phase, combine_partial_ghash reduce phase, validation
+// gate; here CTR and the GHASH map phase are fused into one pass):
+//
+//   k_key_setup / k_key_tables   once per key: round keys, H, H^(2^k), and
+//                                the fixed-multiplier GHASH tables.
+//   k_gcm_tiles                  per wave tile: AES-CTR + XOR + store, and a
+//                                per-lane Horner over the ciphertext with the
+//                                fixed multiplier H^64, then a log-depth
+//                                in-wave combine -> one 16-byte partial.
+//   k_gcm_combine                per message: tree over the tile partials,
+//                                final *H, xor E_K(J0) -> tag / accept flag.
+//   k_gcm_zerofill               zero the output of every rejected message.
+//
+// No MFMA: the work is byte lookups and XORs, not a real-valued contraction.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gcm_internal.h"
+
+namespace gcm {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------- small helpers
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ u32x4 xor3v(u32x4 a, u32x4 b, u32x4 c)
+{
+    return u32x4{xor3(a.x, b.x, c.x), xor3(a.y, b.y, c.y), xor3(a.z, b.z, c.z), xor3(a.w, b.w, c.w)};
+}
+
+__device__ __forceinline__ uint32_t rotl32(uint32_t x, int n) { return n ? (x << n) | (x >> (32 - n)) : x; }
+
+__device__ __forceinline__ uint32_t byte_of(u32x4 a, int k)
+{
+    const uint32_t w = (k < 4) ? a.x : (k < 8) ? a.y : (k < 12) ? a.z : a.w;
+    return (w >> (8 * (k & 3))) & 0xffu;
+}
+
+__device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
+
+__device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// ---------------------------------------------------------------- AES tables
+//
+// S-box from GF(2^8) antilog/log tables with generator 0x03 (FIPS-197 sec.
+// 5.1.1: multiplicative inverse followed by the affine map, written here in
+// its rotate form b ^ rotl(b,1) ^ rotl(b,2) ^ rotl(b,3) ^ rotl(b,4) ^ 0x63).
+// TE0[x] is the MixColumns column (2s, s, s, 3s) as a memory-order word;
+// TE1..TE3 are its byte rotations.
+
+__device__ __forceinline__ uint32_t gf8_xtime(uint32_t a) { return ((a << 1) ^ ((a & 0x80u) ? 0x1bu : 0u)) & 0xffu; }
+
+__device__ __forceinline__ uint32_t rotl8(uint32_t x, int n) { return ((x << n) | (x >> (8 - n))) & 0xffu; }
+
+__global__ void k_init_tables(uint32_t *te0, uint32_t *sbox)
+{
+    __shared__ uint8_t ex[256], lg[256];
+    if (threadIdx.x == 0) {
+        uint32_t x = 1;
+        for (int i = 0; i < 255; ++i) {
+            ex[i] = (uint8_t)x;
+            lg[x] = (uint8_t)i;
+            x = x ^ gf8_xtime(x);  // x * 0x03
+        }
+        lg[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t a = threadIdx.x;
+    if (a < 256) {
+        const uint32_t inv = a ? ex[(255 - lg[a]) % 255] : 0u;
+        const uint32_t s = inv ^ rotl8(inv, 1) ^ rotl8(inv, 2) ^ rotl8(inv, 3) ^ rotl8(inv, 4) ^ 0x63u;
+        const uint32_t s2 = gf8_xtime(s), s3 = s2 ^ s;
+        te0[a] = s2 | (s << 8) | (s << 16) | (s3 << 24);
+        sbox[a] = s;
+    }
+}
+
+// Plain one-block AES from global tables (key setup and E_K(J0) only).
+__device__ void aes_block_global(const uint32_t *rk, int nr, const uint32_t *te0, const uint32_t *sb,
+                                 const uint32_t in[4], uint32_t out[4])
+{
+    uint32_t s0 = in[0] ^ rk[0], s1 = in[1] ^ rk[1], s2 = in[2] ^ rk[2], s3 = in[3] ^ rk[3];
+    for (int r = 1; r < nr; ++r) {
+        const uint32_t t0 = te0[s0 & 0xff] ^ rotl32(te0[(s1 >> 8) & 0xff], 8) ^ rotl32(te0[(s2 >> 16) & 0xff], 16) ^
+                            rotl32(te0[s3 >> 24], 24) ^ rk[4 * r + 0];
+        const uint32_t t1 = te0[s1 & 0xff] ^ rotl32(te0[(s2 >> 8) & 0xff], 8) ^ rotl32(te0[(s3 >> 16) & 0xff], 16) ^
+                            rotl32(te0[s0 >> 24], 24) ^ rk[4 * r + 1];
+        const uint32_t t2 = te0[s2 & 0xff] ^ rotl32(te0[(s3 >> 8) & 0xff], 8) ^ rotl32(te0[(s0 >> 16) & 0xff], 16) ^
+                            rotl32(te0[s1 >> 24], 24) ^ rk[4 * r + 2];
+        const uint32_t t3 = te0[s3 & 0xff] ^ rotl32(te0[(s0 >> 8) & 0xff], 8) ^ rotl32(te0[(s1 >> 16) & 0xff], 16) ^
+                            rotl32(te0[s2 >> 24], 24) ^ rk[4 * r + 3];
+        s0 = t0;
+        s1 = t1;
+        s2 = t2;
+        s3 = t3;
+    }
+    out[0] = (sb[s0 & 0xff] | (sb[(s1 >> 8) & 0xff] << 8) | (sb[(s2 >> 16) & 0xff] << 16) | (sb[s3 >> 24] << 24)) ^
+             rk[4 * nr + 0];
+    out[1] = (sb[s1 & 0xff] | (sb[(s2 >> 8) & 0xff] << 8) | (sb[(s3 >> 16) & 0xff] << 16) | (sb[s0 >> 24] << 24)) ^
+             rk[4 * nr + 1];
+    out[2] = (sb[s2 & 0xff] | (sb[(s3 >> 8) & 0xff] << 8) | (sb[(s0 >> 16) & 0xff] << 16) | (sb[s1 >> 24] << 24)) ^
+             rk[4 * nr + 2];
+    out[3] = (sb[s3 & 0xff] | (sb[(s0 >> 8) & 0xff] << 8) | (sb[(s1 >> 16) & 0xff] << 16) | (sb[s2 >> 24] << 24)) ^
+             rk[4 * nr + 3];
+}
+
+// ---------------------------------------------------------------- key setup
+//
+// FIPS-197 sec. 5.2 key expansion on memory-order words: RotWord is a right
+// rotation by 8 of the little-endian word, Rcon enters byte 0.
+
+struct KeyArg {
+    uint32_t w[8];
+    uint32_t len;
+};
+
+__device__ __forceinline__ uint32_t sub_word(uint32_t t, const uint32_t *sb)
+{
+    return sb[t & 0xff] | (sb[(t >> 8) & 0xff] << 8) | (sb[(t >> 16) & 0xff] << 16) | (sb[t >> 24] << 24);
+}
+
+// GF(2^128) in "polynomial order": bit i of (lo, hi) is the coefficient of
+// x^i.  Memory order is the same bytes with the bits of each byte reversed.
+struct P128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ uint32_t brev_bytes(uint32_t x) { return __builtin_bswap32(__builtin_bitreverse32(x)); }
+
+__device__ __forceinline__ P128 mem_to_poly(const uint32_t m[4])
+{
+    P128 p;
+    p.lo = (uint64_t)brev_bytes(m[0]) | ((uint64_t)brev_bytes(m[1]) << 32);
+    p.hi = (uint64_t)brev_bytes(m[2]) | ((uint64_t)brev_bytes(m[3]) << 32);
+    return p;
+}
+
+__device__ __forceinline__ u32x4 poly_to_mem(P128 p)
+{
+    return u32x4{brev_bytes((uint32_t)p.lo), brev_bytes((uint32_t)(p.lo >> 32)), brev_bytes((uint32_t)p.hi),
+                 brev_bytes((uint32_t)(p.hi >> 32))};
+}
+
+// multiply by x modulo x^128 + x^7 + x^2 + x + 1
+__device__ __forceinline__ P128 poly_mulx(P128 v)
+{
+    const uint64_t carry = v.hi >> 63;
+    v.hi = (v.hi << 1) | (v.lo >> 63);
+    v.lo = (v.lo << 1) ^ (carry ? 0x87ull : 0ull);
+    return v;
+}
+
+// spread the 32 bits of x to the even bit positions of a 64-bit word
+__device__ __forceinline__ uint64_t spread32(uint32_t x)
+{
+    uint64_t v = x;
+    v = (v | (v << 16)) & 0x0000FFFF0000FFFFull;
+    v = (v | (v << 8)) & 0x00FF00FF00FF00FFull;
+    v = (v | (v << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    v = (v | (v << 2)) & 0x3333333333333333ull;
+    v = (v | (v << 1)) & 0x5555555555555555ull;
+    return v;
+}
+
+// squaring is GF(2)-linear: coefficient i moves to 2i, then the upper 128
+// bits fold back through x^128 = x^7 + x^2 + x + 1 (twice at most).
+__device__ P128 poly_square(P128 a)
+{
+    const uint64_t l0 = spread32((uint32_t)a.lo), l1 = spread32((uint32_t)(a.lo >> 32));
+    const uint64_t h0 = spread32((uint32_t)a.hi), h1 = spread32((uint32_t)(a.hi >> 32));
+    // value = (l0, l1) + (h0, h1) * x^128
+    uint64_t tlo = h0 ^ (h0 << 1) ^ (h0 << 2) ^ (h0 << 7);
+    uint64_t thi = h1 ^ ((h1 << 1) | (h0 >> 63)) ^ ((h1 << 2) | (h0 >> 62)) ^ ((h1 << 7) | (h0 >> 57));
+    const uint64_t ov = (h1 >> 63) ^ (h1 >> 62) ^ (h1 >> 57);
+    tlo ^= ov ^ (ov << 1) ^ (ov << 2) ^ (ov << 7);
+    P128 r;
+    r.lo = l0 ^ tlo;
+    r.hi = l1 ^ thi;
+    return r;
+}
+
+// One thread: round keys, H = E_K(0^128), H^(2^k) by repeated squaring.
+__global__ void k_key_setup(KeyArg key, uint8_t *slot, const uint32_t *te0, const uint32_t *sb)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0)
+        return;
+    KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(slot);
+    const int nk = (int)key.len / 4, nr = nk + 6;
+    uint32_t w[4 * (kMaxNr + 1)];
+    for (int i = 0; i < nk; ++i)
+        w[i] = key.w[i];
+    uint32_t rcon = 1;
+    for (int i = nk; i < 4 * (nr + 1); ++i) {
+        uint32_t t = w[i - 1];
+        if (i % nk == 0) {
+            t = sub_word((t >> 8) | (t << 24), sb) ^ rcon;
+            rcon = gf8_xtime(rcon);
+        } else if (nk > 6 && i % nk == 4) {
+            t = sub_word(t, sb);
+        }
+        w[i] = w[i - nk] ^ t;
+    }
+    for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
+        hd->rk[i] = i < 4 * (nr + 1) ? w[i] : 0u;
+    hd->nr = (uint32_t)nr;
+    hd->key_len = key.len;
+    const uint32_t zero[4] = {0, 0, 0, 0};
+    uint32_t h[4];
+    aes_block_global(w, nr, te0, sb, zero, h);
+    for (int i = 0; i < 4; ++i)
+        hd->h[i] = h[i];
+    P128 p = mem_to_poly(h);
+    for (int k = 0; k < kPowLevels; ++k) {
+        const u32x4 m = poly_to_mem(p);
+        hd->hpow[k][0] = m.x;
+        hd->hpow[k][1] = m.y;
+        hd->hpow[k][2] = m.z;
+        hd->hpow[k][3] = m.w;
+        p = poly_square(p);
+    }
+}
+
+// Fixed-multiplier tables.  Block b < kTab4Levels builds the nibble-position
+// table of H^(2^b); the last block builds the byte-position table of
+// H^(2^kStrideLevel) = H^64, the per-lane Horner multiplier of the tile kernel.
+__global__ __launch_bounds__(256) void k_key_tables(uint8_t *slot)
+{
+    __shared__ u32x4 basis[128];  // basis[i] = M * x^i, memory order
+    const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
+    const int b = blockIdx.x;
+    const int lvl = b < kTab4Levels ? b : kStrideLevel;
+    const int tid = threadIdx.x;
+    if (tid < 128) {
+        P128 v = mem_to_poly(hd->hpow[lvl]);
+        for (int s = 0; s < tid; ++s)
+            v = poly_mulx(v);
+        basis[tid] = poly_to_mem(v);
+    }
+    __syncthreads();
+    if (b < kTab4Levels) {
+        u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes);
+        for (int e = tid; e < 512; e += 256) {
+            const int j = e >> 4, nib = e & 15;
+            const int byte = j >> 1, shift = (j & 1) ? 0 : 4;  // even j: high nibble
+            u32x4 acc = {0, 0, 0, 0};
+            for (int t = 0; t < 4; ++t)
+                if ((nib >> t) & 1)
+                    acc ^= basis[8 * byte + 7 - (t + shift)];
+            tab[e] = acc;
+        }
+    } else {
+        u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab8Off);
+        for (int e = tid; e < 4096; e += 256) {
+            const int k = e >> 8, v = e & 255;
+            u32x4 acc = {0, 0, 0, 0};
+            for (int s = 0; s < 8; ++s)
+                if ((v >> s) & 1)
+                    acc ^= basis[8 * k + 7 - s];
+            tab[e] = acc;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- GF(2^128) by table
+
+// a * M with the nibble-position table of M (global memory, 32 gathers)
+__device__ __forceinline__ u32x4 mul_tab4(u32x4 a, const u32x4 *__restrict__ tab)
+{
+    u32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t byte = byte_of(a, k);
+        r0 ^= tab[(2 * k) * 16 + (byte >> 4)];
+        r1 ^= tab[(2 * k + 1) * 16 + (byte & 15)];
+    }
+    return r0 ^ r1;
+}
+
+// a * H^e for 0 <= e < 2^bits using the tables of H^(2^(level0 + k))
+__device__ __forceinline__ u32x4 mul_hpow(u32x4 a, uint64_t e, int bits, const uint8_t *slot, int level0)
+{
+    for (int k = 0; k < bits; ++k) {
+        const u32x4 *tab = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off + (uint64_t)(level0 + k) * kTab4Bytes);
+        const u32x4 m = mul_tab4(a, tab);
+        if ((e >> k) & 1)
+            a = m;
+    }
+    return a;
+}
+
+__device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        a.x ^= __shfl_xor(a.x, off, 64);
+        a.y ^= __shfl_xor(a.y, off, 64);
+        a.z ^= __shfl_xor(a.z, off, 64);
+        a.w ^= __shfl_xor(a.w, off, 64);
+    }
+    return a;
+}
+
+// ---------------------------------------------------------------- fused tile kernel
+//
+// LDS: [0, 4 KiB) the four AES T-tables (so byte<<2 indexes them with an
+// immediate table offset), [4 KiB, 68 KiB) the byte-position GHASH table of
+// H^64 for the current key.
+
+constexpr int kLdsTeWords = 1024;
+constexpr int kLdsVec = 256 + 4096;  // u32x4 units
+
+struct AesCtx {
+    const uint32_t *te;  // LDS
+    uint32_t u0, u1, u2, u3;  // round-1 columns with the 12 IV bytes folded in
+    uint32_t rk3;             // round key 0, column 3
+};
+
+#define TE(r, x) te[(r) * 256 + (x)]
+#define B0(x) ((x) & 0xffu)
+#define B1(x) (((x) >> 8) & 0xffu)
+#define B2(x) (((x) >> 16) & 0xffu)
+#define B3(x) ((x) >> 24)
+
+// Keystream block for counter value `ctr` (big-endian in bytes 12..15).
+// Only column 3 of the counter block varies, so round 1 needs four table
+// lookups instead of sixteen (counter-mode caching).
+template <int NR>
+__device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const uint32_t *__restrict__ rk)
+{
+    const uint32_t *te = c.te;
+    const uint32_t v = bswap32(ctr) ^ c.rk3;
+    uint32_t s0 = c.u0 ^ TE(3, B3(v));
+    uint32_t s1 = c.u1 ^ TE(2, B2(v));
+    uint32_t s2 = c.u2 ^ TE(1, B1(v));
+    uint32_t s3 = c.u3 ^ TE(0, B0(v));
+#pragma unroll
+    for (int r = 2; r < NR; ++r) {
+        const uint32_t t0 = xor3(xor3(TE(0, B0(s0)), TE(1, B1(s1)), TE(2, B2(s2))), TE(3, B3(s3)), rk[4 * r + 0]);
+        const uint32_t t1 = xor3(xor3(TE(0, B0(s1)), TE(1, B1(s2)), TE(2, B2(s3))), TE(3, B3(s0)), rk[4 * r + 1]);
+        const uint32_t t2 = xor3(xor3(TE(0, B0(s2)), TE(1, B1(s3)), TE(2, B2(s0))), TE(3, B3(s1)), rk[4 * r + 2]);
+        const uint32_t t3 = xor3(xor3(TE(0, B0(s3)), TE(1, B1(s0)), TE(2, B2(s1))), TE(3, B3(s2)), rk[4 * r + 3]);
+        s0 = t0;
+        s1 = t1;
+        s2 = t2;
+        s3 = t3;
+    }
+    // last round: S-box only; TE2 holds S(x) in byte 0, TE3 in byte 1, TE0 in byte 2, TE1 in byte 3
+    u32x4 o;
+    o.x = ((TE(2, B0(s0)) & 0x000000ffu) | (TE(3, B1(s1)) & 0x0000ff00u) | (TE(0, B2(s2)) & 0x00ff0000u) |
+           (TE(1, B3(s3)) & 0xff000000u)) ^ rk[4 * NR + 0];
+    o.y = ((TE(2, B0(s1)) & 0x000000ffu) | (TE(3, B1(s2)) & 0x0000ff00u) | (TE(0, B2(s3)) & 0x00ff0000u) |
+           (TE(1, B3(s0)) & 0xff000000u)) ^ rk[4 * NR + 1];
+    o.z = ((TE(2, B0(s2)) & 0x000000ffu) | (TE(3, B1(s3)) & 0x0000ff00u) | (TE(0, B2(s0)) & 0x00ff0000u) |
+           (TE(1, B3(s1)) & 0xff000000u)) ^ rk[4 * NR + 2];
+    o.w = ((TE(2, B0(s3)) & 0x000000ffu) | (TE(3, B1(s0)) & 0x0000ff00u) | (TE(0, B2(s1)) & 0x00ff0000u) |
+           (TE(1, B3(s2)) & 0xff000000u)) ^ rk[4 * NR + 3];
+    return o;
+}
+
+// a * H^64 with the byte-position table in LDS (16 lookups of 16 bytes)
+__device__ __forceinline__ u32x4 ghash_mul8(u32x4 a, const u32x4 *__restrict__ tab)
+{
+    u32x4 e[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        e[k] = tab[k * 256 + byte_of(a, k)];
+    const u32x4 p0 = xor3v(e[0], e[1], e[2]);
+    const u32x4 p1 = xor3v(e[3], e[4], e[5]);
+    const u32x4 p2 = xor3v(e[6], e[7], e[8]);
+    const u32x4 p3 = xor3v(e[9], e[10], e[11]);
+    const u32x4 p4 = xor3v(e[12], e[13], e[14]);
+    return xor3v(xor3v(p0, p1, p2), xor3v(p3, p4, e[15]), u32x4{0, 0, 0, 0});
+}
+
+// zero-padded load of block `blk` of a buffer of `total` bytes
+__device__ __forceinline__ u32x4 load_block_partial(const uint8_t *p, uint64_t blk, uint64_t total)
+{
+    const uint64_t off = blk * 16;
+    if (off + 16 <= total)
+        return *reinterpret_cast<const u32x4 *>(p + off);
+    uint32_t w[4] = {0, 0, 0, 0};
+    for (uint64_t k = off; k < total; ++k)
+        w[(k - off) >> 2] |= (uint32_t)p[k] << (8 * ((k - off) & 3));
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__device__ __forceinline__ u32x4 mask_block(u32x4 v, uint64_t blk, uint64_t total)
+{
+    const uint64_t off = blk * 16;
+    if (off + 16 <= total)
+        return v;
+    const uint32_t nb = (uint32_t)(total - off);  // 1..15 valid bytes
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    for (int d = 0; d < 4; ++d) {
+        const int lo = 4 * d;
+        if ((int)nb <= lo)
+            w[d] = 0;
+        else if ((int)nb < lo + 4)
+            w[d] &= (1u << (8 * (nb - lo))) - 1u;
+    }
+    return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, uint64_t total, u32x4 v)
+{
+    const uint64_t off = blk * 16;
+    if (off + 16 <= total) {
+        *reinterpret_cast<u32x4 *>(p + off) = v;
+        return;
+    }
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    for (uint64_t k = off; k < total; ++k)
+        p[k] = (uint8_t)(w[(k - off) >> 2] >> (8 * ((k - off) & 3)));
+}
+
+// One wave processes wave tile t of message d: rows of 64 consecutive
+// blocks, lane l on block 64*r + l, so every load/store instruction moves one
+// contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
+// p_t = sum_l a_l * H^(63-l) is formed by squaring-style fix-ups and an XOR
+// across the wave.
+template <int NR>
+__device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint32_t *__restrict__ te,
+                          const u32x4 *__restrict__ tab8, u32x4 *__restrict__ partials)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t *__restrict__ rk = reinterpret_cast<const KeySlotHdr *>(d.slot)->rk;
+
+    AesCtx c;
+    c.te = te;
+    {
+        const uint32_t s0 = d.iv[0] ^ rk[0], s1 = d.iv[1] ^ rk[1], s2 = d.iv[2] ^ rk[2];
+        c.u0 = uniform(TE(0, B0(s0)) ^ TE(1, B1(s1)) ^ TE(2, B2(s2)) ^ rk[4]);
+        c.u1 = uniform(TE(0, B0(s1)) ^ TE(1, B1(s2)) ^ TE(3, B3(s0)) ^ rk[5]);
+        c.u2 = uniform(TE(0, B0(s2)) ^ TE(2, B2(s0)) ^ TE(3, B3(s1)) ^ rk[6]);
+        c.u3 = uniform(TE(1, B1(s0)) ^ TE(2, B2(s1)) ^ TE(3, B3(s2)) ^ rk[7]);
+        c.rk3 = rk[3];
+    }
+
+    const uint64_t B = 1ull << d.log2B;
+    const uint32_t R = (uint32_t)(B >> 6);
+    const int64_t vbase = (int64_t)(t * B) - (int64_t)d.z;  // GHASH index of lane 0, row 0
+    const uint32_t r0 = vbase < 0 ? (uint32_t)((uint64_t)(-vbase) >> 6) : 0u;
+    const int64_t na = (int64_t)d.na;
+    const int64_t nfull = (int64_t)(d.len >> 4);
+    const int64_t ndat = (int64_t)d.n;
+    const bool enc = d.op == 0;
+    const uint8_t *__restrict__ in = reinterpret_cast<const uint8_t *>(d.in);
+    uint8_t *__restrict__ out = reinterpret_cast<uint8_t *>(d.out);
+
+    u32x4 a = {0, 0, 0, 0};
+    for (uint32_t r = r0; r < R; ++r) {
+        const int64_t v0 = vbase + 64 * (int64_t)r;
+        if (v0 >= na && v0 + 64 <= na + nfull) {
+            // all 64 lanes hold whole data blocks
+            const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
+            const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(in) + j);
+            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk);
+            const u32x4 o = x ^ ks;
+            __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(out) + j);
+            a = ghash_mul8(a, tab8) ^ (enc ? o : x);
+        } else {
+            // boundary row: zero padding, AAD, partial blocks or the length block
+            const int64_t v = v0 + lane;
+            const uint64_t j = (uint64_t)(v - na);
+            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk);
+            u32x4 X = {0, 0, 0, 0};
+            if (v >= 0 && v < na) {
+                X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
+            } else if (v >= na && v < na + ndat) {
+                const u32x4 x = load_block_partial(in, j, d.len);
+                const u32x4 o = x ^ ks;
+                store_block_partial(out, j, d.len, o);
+                X = enc ? mask_block(o, j, d.len) : x;
+            } else if (v == na + ndat) {
+                const uint64_t abits = d.aad_len * 8, cbits = d.len * 8;
+                X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
+                          bswap32((uint32_t)cbits)};
+            }
+            a = ghash_mul8(a, tab8) ^ X;
+        }
+    }
+
+    // fix-up: a * H^(63 - lane), exponent bits through the H^(2^k) tables
+    a = mul_hpow(a, (uint64_t)(63 - lane), 6, reinterpret_cast<const uint8_t *>(d.slot), 0);
+    a = wave_xor_reduce(a);
+    if (lane == 0)
+        partials[d.tile_base + t] = a;
+}
+
+template <int NR>
+__device__ __forceinline__ void wave_tile_dispatch(const MsgDesc &d, uint64_t t, const uint32_t *te, const u32x4 *tab8,
+                                                   u32x4 *partials)
+{
+    wave_tile<NR>(d, t, te, tab8, partials);
+}
+
+template <int WAVES, bool BATCH>
+__global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restrict__ descs,
+                                                          const WorkItem *__restrict__ items, uint32_t n_items,
+                                                          MsgDesc single, const uint32_t *__restrict__ te0g,
+                                                          u32x4 *__restrict__ partials, uint32_t *counters)
+{
+    __shared__ u32x4 lds[kLdsVec];
+    uint32_t *te = reinterpret_cast<uint32_t *>(lds);
+    u32x4 *tab8 = lds + 256;
+
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        counters[0] = 0;  // reject count for this launch (read by the zero-fill)
+
+    for (int i = threadIdx.x; i < kLdsTeWords; i += WAVES * 64)
+        te[i] = rotl32(te0g[i & 255], 8 * (i >> 8));
+
+    uint64_t cur_slot = 0;
+    const int wave = threadIdx.x >> 6;
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        MsgDesc d;
+        uint32_t first;
+        if (BATCH) {
+            const WorkItem w = items[it];
+            d = descs[w.msg];
+            first = w.first_tile;
+        } else {
+            d = single;
+            first = it * WAVES;
+        }
+        if (d.slot != cur_slot) {
+            __syncthreads();
+            const u32x4 *src = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab8Off);
+            for (int i = threadIdx.x; i < 4096; i += WAVES * 64)
+                tab8[i] = src[i];
+            cur_slot = d.slot;
+            __syncthreads();
+        }
+        const uint64_t t = (uint64_t)first + (uint64_t)wave;
+        if (t < d.n_tiles) {
+            if (d.nr == 10)
+                wave_tile_dispatch<10>(d, t, te, tab8, partials);
+            else if (d.nr == 12)
+                wave_tile_dispatch<12>(d, t, te, tab8, partials);
+            else
+                wave_tile_dispatch<14>(d, t, te, tab8, partials);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- combine + tag
+
+constexpr int kCombineThreads = 1024;
+constexpr int kCombineLog2 = 10;
+
+// S = sum_t p_t * H^((T-1-t)*B + 1); tag = S xor E_K(J0).  Thread i runs a
+// Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B),
+// then lifts its value by H^((T-1-t_last)*B); the XOR over threads closes
+// the tree, and one more *H accounts for GHASH's final multiplication.
+template <bool BATCH>
+__global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
+                                                                 const uint32_t *__restrict__ te0g,
+                                                                 const uint32_t *__restrict__ sbg,
+                                                                 const u32x4 *__restrict__ partials,
+                                                                 uint32_t *counters)
+{
+    __shared__ u32x4 red[kCombineThreads / 64];
+    const MsgDesc d = BATCH ? descs[blockIdx.x] : single;
+    const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
+    const uint32_t i = threadIdx.x;
+    const uint64_t T = d.n_tiles;
+
+    u32x4 acc = {0, 0, 0, 0};
+    if (i < T) {
+        const u32x4 *tabS = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off +
+                                                            (uint64_t)(d.log2B + kCombineLog2) * kTab4Bytes);
+        uint64_t t = i, t_last = i;
+        for (; t < T; t += kCombineThreads) {
+            acc = mul_tab4(acc, tabS) ^ partials[d.tile_base + t];
+            t_last = t;
+        }
+        acc = mul_hpow(acc, T - 1 - t_last, kCombineLog2, slot, (int)d.log2B);
+    }
+    acc = wave_xor_reduce(acc);
+    if ((i & 63) == 0)
+        red[i >> 6] = acc;
+    __syncthreads();
+    if (i == 0) {
+        u32x4 s = red[0];
+        for (int w = 1; w < kCombineThreads / 64; ++w)
+            s ^= red[w];
+        s = mul_tab4(s, reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off));  // * H
+        const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
+        const uint32_t j0[4] = {d.iv[0], d.iv[1], d.iv[2], 0x01000000u};
+        uint32_t ek[4];
+        aes_block_global(hd->rk, (int)hd->nr, te0g, sbg, j0, ek);
+        const u32x4 tag = s ^ u32x4{ek[0], ek[1], ek[2], ek[3]};
+        if (d.op == 0) {
+            *reinterpret_cast<u32x4 *>(d.tag) = tag;
+        } else {
+            const uint8_t *exp = reinterpret_cast<const uint8_t *>(d.tag);
+            uint32_t diff = 0;
+            const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
+            for (int k = 0; k < 16; ++k)
+                diff |= ((tw[k >> 2] >> (8 * (k & 3))) & 0xffu) ^ exp[k];
+            const int32_t ok = diff == 0 ? 1 : 0;
+            *reinterpret_cast<int32_t *>(d.ok) = ok;
+            if (!ok) {
+                const uint32_t pos = atomicAdd(&counters[0], 1u);
+                counters[1 + pos] = BATCH ? blockIdx.x : 0u;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- zero-fill on reject
+
+template <bool BATCH>
+__global__ __launch_bounds__(256) void k_gcm_zerofill(const MsgDesc *__restrict__ descs, MsgDesc single,
+                                                      const uint32_t *__restrict__ counters)
+{
+    const uint32_t n_rej = counters[0];
+    for (uint32_t q = 0; q < n_rej; ++q) {
+        const MsgDesc d = BATCH ? descs[counters[1 + q]] : single;
+        uint8_t *out = reinterpret_cast<uint8_t *>(d.out);
+        const uint64_t nfull = d.len >> 4;
+        const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+        for (uint64_t j = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nfull; j += stride)
+            __builtin_nontemporal_store(u32x4{0, 0, 0, 0}, reinterpret_cast<u32x4 *>(out) + j);
+        if (blockIdx.x == 0 && threadIdx.x < (d.len & 15))
+            out[nfull * 16 + threadIdx.x] = 0;
+    }
+}
+
+// ---------------------------------------------------------------- host-side launchers
+
+hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init_tables, dim3(1), dim3(256), 0, s, te0, sbox);
+    return hipGetLastError();
+}
+
+hipError_t launch_key_setup(const uint8_t *key, uint32_t key_len, uint8_t *slot, const uint32_t *te0,
+                            const uint32_t *sbox, hipStream_t s)
+{
+    KeyArg ka{};
+    for (uint32_t i = 0; i < key_len / 4; ++i)
+        ka.w[i] = (uint32_t)key[4 * i] | ((uint32_t)key[4 * i + 1] << 8) | ((uint32_t)key[4 * i + 2] << 16) |
+                  ((uint32_t)key[4 * i + 3] << 24);
+    ka.len = key_len;
+    hipLaunchKernelGGL(k_key_setup, dim3(1), dim3(64), 0, s, ka, slot, te0, sbox);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1), dim3(256), 0, s, slot);
+    return hipGetLastError();
+}
+
+template <int WAVES>
+static hipError_t launch_tiles_w(const MsgDesc *descs, const WorkItem *items, uint32_t n_items, const MsgDesc *single,
+                                 const uint32_t *te0, u32x4 *partials, uint32_t *counters, uint32_t grid,
+                                 hipStream_t s)
+{
+    if (descs)
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, descs, items, n_items,
+                           MsgDesc{}, te0, partials, counters);
+    else
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
+                           n_items, *single, te0, partials, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, uint32_t n_items,
+                        const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
+                        hipStream_t s)
+{
+    u32x4 *p = reinterpret_cast<u32x4 *>(partials);
+    switch (waves) {
+    case 4:
+        return launch_tiles_w<4>(descs, items, n_items, single, te0, p, counters, grid, s);
+    case 8:
+        return launch_tiles_w<8>(descs, items, n_items, single, te0, p, counters, grid, s);
+    case 16:
+        return launch_tiles_w<16>(descs, items, n_items, single, te0, p, counters, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+int max_groups_per_cu(int waves)
+{
+    int n = 0;
+    hipError_t e = hipErrorInvalidValue;
+    switch (waves) {
+    case 4:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<4, false>, 4 * 64, 0);
+        break;
+    case 8:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false>, 8 * 64, 0);
+        break;
+    case 16:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false>, 16 * 64, 0);
+        break;
+    }
+    return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const uint32_t *te0,
+                          const uint32_t *sbox, const void *partials, uint32_t *counters, hipStream_t s)
+{
+    const u32x4 *p = reinterpret_cast<const u32x4 *>(partials);
+    if (descs)
+        hipLaunchKernelGGL(k_gcm_combine<true>, dim3(n_msgs), dim3(kCombineThreads), 0, s, descs, MsgDesc{}, te0, sbox,
+                           p, counters);
+    else
+        hipLaunchKernelGGL(k_gcm_combine<false>, dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, te0, sbox, p,
+                           counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
+                           hipStream_t s)
+{
+    if (descs)
+        hipLaunchKernelGGL(k_gcm_zerofill<true>, dim3(grid), dim3(256), 0, s, descs, MsgDesc{}, counters);
+    else
+        hipLaunchKernelGGL(k_gcm_zerofill<false>, dim3(grid), dim3(256), 0, s, nullptr, *single, counters);
+    return hipGetLastError();
+}
+
+}  // namespace gcm

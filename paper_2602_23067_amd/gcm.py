@@ -1,0 +1,176 @@
+"""Thin ctypes binding over ``libgcm_mi355.so`` (argument marshalling only).
+
+Every step of AES-GCM runs in the library's HIP kernels; this module only
+turns torch tensors into device pointers and HIP stream handles and checks
+return codes.  It raises ``ImportError`` when the library has not been
+built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgcm_mi355.so")
+
+GCM_OK = 0
+GCM_E_ARG = -1
+GCM_E_KEYLEN = -2
+GCM_E_IVLEN = -3
+GCM_E_TOOLONG = -4
+GCM_E_NOMEM = -5
+GCM_E_HIP = -6
+GCM_E_BUSY = -7
+GCM_E_ALIAS = -8
+GCM_E_SLOT = -9
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+class GcmError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2602_23067_amd.build.build() "
+                          "(there is no non-GPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, u64, u32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint64, ctypes.c_uint32
+    i32p = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "gcm_ctx_create": ([ctypes.POINTER(vp), ctypes.c_int, u64, u32], ctypes.c_int),
+        "gcm_ctx_destroy": ([vp], ctypes.c_int),
+        "gcm_last_error": ([], ctypes.c_char_p),
+        "gcm_key_register": ([vp, vp, sz, ctypes.POINTER(u32), vp], ctypes.c_int),
+        "gcm_key_release": ([vp, u32], ctypes.c_int),
+        "gcm_encrypt": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, vp], ctypes.c_int),
+        "gcm_decrypt_verify": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, i32p, vp], ctypes.c_int),
+        "gcm_workspace_size": ([vp, u64, u64], u64),
+        "gcm_encrypt_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, u64, vp], ctypes.c_int),
+        "gcm_decrypt_verify_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, vp, u64, vp], ctypes.c_int),
+        "gcm_set_launch": ([vp, u32, u32, u32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int) -> int:
+    if rc != GCM_OK:
+        raise GcmError(rc, load().gcm_last_error().decode(errors="replace"))
+    return rc
+
+
+def _dev(t) -> int:
+    """Device address of a contiguous uint8 CUDA tensor (0 for None/empty)."""
+    if t is None:
+        return 0
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError("payload tensors must live on the GPU")
+    if t.dtype != torch.uint8:
+        raise TypeError("payload tensors must be uint8")
+    if not t.is_contiguous():
+        raise ValueError("payload tensors must be contiguous")
+    return t.data_ptr() if t.numel() else 0
+
+
+def _stream(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _host(b: bytes) -> ctypes.Array:
+    return ctypes.create_string_buffer(bytes(b), len(b))
+
+
+class Context:
+    """An AES-GCM context on one GPU (key table, scratch, tuning)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0, key_slots: int = 64):
+        L = load()
+        h = ctypes.c_void_p()
+        _check(L.gcm_ctx_create(ctypes.byref(h), device, hbm_budget, key_slots))
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gcm_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    # -------------------------------------------------------- keys
+    def key_register(self, key: bytes, stream=None) -> int:
+        slot = ctypes.c_uint32()
+        _check(load().gcm_key_register(self._h, _host(key), len(key), ctypes.byref(slot), _stream(stream)))
+        return slot.value
+
+    def key_release(self, slot: int) -> None:
+        _check(load().gcm_key_release(self._h, slot))
+
+    # -------------------------------------------------------- one-shot
+    def encrypt(self, key: bytes, iv: bytes, aad, pt, ct, stream=None) -> bytes:
+        tag = ctypes.create_string_buffer(16)
+        _check(load().gcm_encrypt(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
+                                  0 if aad is None else aad.numel(), _dev(pt), pt.numel(), _dev(ct), tag,
+                                  _stream(stream)))
+        return tag.raw
+
+    def decrypt_verify(self, key: bytes, iv: bytes, aad, ct, tag: bytes, pt, stream=None) -> bool:
+        acc = ctypes.c_int(-1)
+        _check(load().gcm_decrypt_verify(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
+                                         0 if aad is None else aad.numel(), _dev(ct), ct.numel(), _host(tag),
+                                         _dev(pt), ctypes.byref(acc), _stream(stream)))
+        return acc.value == 1
+
+    # -------------------------------------------------------- async, resident key
+    def workspace_size(self, length: int, aad_len: int) -> int:
+        return int(load().gcm_workspace_size(self._h, length, aad_len))
+
+    def encrypt_async(self, slot: int, iv: bytes, aad, pt, ct, tag_d, workspace, stream=None) -> None:
+        _check(load().gcm_encrypt_async(self._h, slot, _host(iv), len(iv), _dev(aad),
+                                        0 if aad is None else aad.numel(), _dev(pt), pt.numel(), _dev(ct),
+                                        _dev(tag_d), _dev(workspace), workspace.numel(), _stream(stream)))
+
+    def decrypt_verify_async(self, slot: int, iv: bytes, aad, ct, tag_d, pt, accept_d, workspace,
+                             stream=None) -> None:
+        _check(load().gcm_decrypt_verify_async(self._h, slot, _host(iv), len(iv), _dev(aad),
+                                               0 if aad is None else aad.numel(), _dev(ct), ct.numel(),
+                                               _dev(tag_d), _dev(pt), accept_d.data_ptr(), _dev(workspace),
+                                               workspace.numel(), _stream(stream)))
+
+    # -------------------------------------------------------- tuning
+    def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
+        _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))

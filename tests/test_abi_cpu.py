@@ -1,0 +1,54 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports
+every function the public headers declare."""
+import ctypes
+import glob
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_ ]*?[\s\*]+(gcm_[a-z0-9_]+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for need in ("gcm_ctx_create", "gcm_ctx_destroy", "gcm_last_error", "gcm_encrypt", "gcm_decrypt_verify",
+                 "gcm_key_register", "gcm_key_release", "gcm_encrypt_async", "gcm_decrypt_verify_async"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2602_23067_amd import gcm
+
+    if not os.path.exists(gcm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = ctypes.CDLL(gcm.LIB_PATH)
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    from paper_2602_23067_amd import gcm
+
+    monkeypatch.setattr(gcm, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(gcm, "_lib", None)
+    with pytest.raises(ImportError):
+        gcm.load()
+
+
+def test_last_error_is_a_string_before_any_call():
+    from paper_2602_23067_amd import gcm
+
+    if not os.path.exists(gcm.LIB_PATH):
+        pytest.skip("library not built")
+    assert isinstance(gcm.load().gcm_last_error(), bytes)

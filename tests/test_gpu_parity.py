@@ -1,0 +1,210 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle, bit for bit.
+
+Sizes here let the oracle finish in seconds while still spanning several
+wave tiles and ragged tails; launch shapes are forced small so that even
+short messages cross many tiles.
+"""
+import random
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2602_23067_amd import gcm, workloads  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import canaries_intact, guarded, host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = gcm.Context(device=0, key_slots=64)
+    yield c
+    c.close()
+
+
+def _enc(ctx, key, iv, aad, pt):
+    aad_d = to_dev(aad) if len(aad) else None
+    pt_d = to_dev(pt)
+    ct_d = torch.empty_like(pt_d)
+    tag = ctx.encrypt(key, iv, aad_d, pt_d, ct_d)
+    return host(ct_d), tag
+
+
+def _dec(ctx, key, iv, aad, ct, tag):
+    aad_d = to_dev(aad) if len(aad) else None
+    ct_d = to_dev(ct)
+    pt_d = torch.full_like(ct_d, 0x5A)
+    ok = ctx.decrypt_verify(key, iv, aad_d, ct_d, tag, pt_d)
+    return host(pt_d), ok
+
+
+def _check_case(ctx, key, iv, aad, pt):
+    rct, rtag = oracle.gcm_encrypt(key, iv, aad, pt)
+    ct, tag = _enc(ctx, key, iv, aad, pt)
+    assert np.array_equal(ct, rct), "ciphertext differs from the oracle"
+    assert tag == rtag, "tag differs from the oracle"
+    back, ok = _dec(ctx, key, iv, aad, ct, tag)
+    assert ok and np.array_equal(back, np.asarray(pt, dtype=np.uint8))
+
+
+def test_config1_parity(ctx):
+    m = workloads.config1()
+    print(f"config1: len={m.data.size} aad={m.aad.size}", flush=True)
+    _check_case(ctx, m.key, m.iv, m.aad, m.data)
+
+
+@pytest.mark.parametrize("log2B", [6, 8])
+def test_tail_sweep(ctx, log2B):
+    ctx.set_launch(log2B, 4, 1)
+    try:
+        r = workloads.rng_for(7, log2B)
+        sizes = list(range(0, 70)) + [255, 256, 257, 1023, 1024, 1025, 1040, 4095, 4096, 4097, 12345]
+        for n in sizes:
+            alen = int(r.choice([0, 1, 15, 16, 17, 100, 1024, 2880]))
+            key = workloads.random_bytes(r, int(r.choice([16, 32]))).tobytes()
+            iv = workloads.random_bytes(r, 12).tobytes()
+            aad = workloads.random_bytes(r, alen)
+            pt = workloads.random_bytes(r, n)
+            _check_case(ctx, key, iv, aad, pt)
+    finally:
+        ctx.set_launch(0, 0, 0)
+
+
+@pytest.mark.parametrize("key_len", [16, 24, 32])
+def test_key_sizes(ctx, key_len):
+    r = workloads.rng_for(11, key_len)
+    key = workloads.random_bytes(r, key_len).tobytes()
+    iv = workloads.random_bytes(r, 12).tobytes()
+    _check_case(ctx, key, iv, workloads.random_bytes(r, 33), workloads.random_bytes(r, 70001))
+
+
+@pytest.mark.parametrize("shape", [(6, 4, 1), (7, 8, 1), (9, 16, 1), (10, 8, 2), (12, 4, 3), (0, 0, 0)])
+def test_geometry_invariance(ctx, shape):
+    """The paper's geometry-agnostic counter map: identical bits for every launch shape."""
+    r = workloads.rng_for(13)
+    key = workloads.random_bytes(r, 32).tobytes()
+    iv = workloads.random_bytes(r, 12).tobytes()
+    aad = workloads.random_bytes(r, 2880)
+    pt = workloads.random_bytes(r, 300_007)
+    ctx.set_launch(*shape)
+    try:
+        _check_case(ctx, key, iv, aad, pt)
+    finally:
+        ctx.set_launch(0, 0, 0)
+
+
+def test_in_place_equals_out_of_place(ctx):
+    r = workloads.rng_for(17)
+    key, iv = workloads.random_bytes(r, 16).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    aad = to_dev(workloads.random_bytes(r, 20))
+    pt = workloads.random_bytes(r, 100_003)
+    rct, rtag = oracle.gcm_encrypt(key, iv, host(aad), pt)
+    buf = to_dev(pt)
+    tag = ctx.encrypt(key, iv, aad, buf, buf)
+    assert tag == rtag and np.array_equal(host(buf), rct)
+    ok = ctx.decrypt_verify(key, iv, aad, buf, tag, buf)
+    assert ok and np.array_equal(host(buf), pt)
+
+
+def test_no_write_outside_output(ctx):
+    r = workloads.rng_for(19)
+    key, iv = workloads.random_bytes(r, 32).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    for n in (1, 15, 17, 4097, 65541):
+        pt = workloads.random_bytes(r, n)
+        full, view = guarded(n)
+        tag = ctx.encrypt(key, iv, None, to_dev(pt), view)
+        assert canaries_intact(full, n)
+        rct, rtag = oracle.gcm_encrypt(key, iv, b"", pt)
+        assert tag == rtag and np.array_equal(host(view), rct)
+        full2, view2 = guarded(n)
+        bad = bytes([tag[0] ^ 1]) + tag[1:]
+        ok = ctx.decrypt_verify(key, iv, None, to_dev(rct), bad, view2)
+        assert not ok and canaries_intact(full2, n) and not host(view2).any()
+
+
+def test_tampering_rejected_and_zero_filled(ctx):
+    r = workloads.rng_for(23)
+    key, iv = workloads.random_bytes(r, 16).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    aad = workloads.random_bytes(r, 45)
+    pt = workloads.random_bytes(r, 200_001)
+    ct, tag = oracle.gcm_encrypt(key, iv, aad, pt)
+    rnd = random.Random(5)
+    for _ in range(6):
+        bad = ct.copy()
+        pos = rnd.randrange(bad.size)
+        bad[pos] ^= 1 << rnd.randrange(8)
+        out, ok = _dec(ctx, key, iv, aad, bad, tag)
+        assert not ok and not out.any()
+    for bit in (0, 77, 127):
+        t = bytearray(tag)
+        t[bit // 8] ^= 1 << (bit % 8)
+        out, ok = _dec(ctx, key, iv, aad, ct, bytes(t))
+        assert not ok and not out.any()
+    bad_aad = aad.copy()
+    bad_aad[3] ^= 0x10
+    out, ok = _dec(ctx, key, iv, bad_aad, ct, tag)
+    assert not ok and not out.any()
+    out, ok = _dec(ctx, bytes(16), iv, aad, ct, tag)
+    assert not ok and not out.any()
+
+
+def test_async_resident_key(ctx):
+    r = workloads.rng_for(29)
+    key, iv = workloads.random_bytes(r, 32).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    aad = workloads.random_bytes(r, 100)
+    pt = workloads.random_bytes(r, 123_457)
+    slot = ctx.key_register(key)
+    try:
+        ws = torch.zeros(ctx.workspace_size(pt.size, aad.size), dtype=torch.uint8, device="cuda")
+        tag_d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        aad_d, pt_d = to_dev(aad), to_dev(pt)
+        ct_d = torch.empty_like(pt_d)
+        ctx.encrypt_async(slot, iv, aad_d, pt_d, ct_d, tag_d, ws)
+        rct, rtag = oracle.gcm_encrypt(key, iv, aad, pt)
+        assert bytes(host(tag_d)) == rtag and np.array_equal(host(ct_d), rct)
+        acc = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+        back = torch.empty_like(ct_d)
+        ctx.decrypt_verify_async(slot, iv, aad_d, ct_d, tag_d, back, acc, ws)
+        assert int(host(acc)[0]) == 1 and np.array_equal(host(back), pt)
+        tag_d[0] ^= 1
+        ctx.decrypt_verify_async(slot, iv, aad_d, ct_d, tag_d, back, acc, ws)
+        assert int(host(acc)[0]) == 0 and not host(back).any()
+    finally:
+        ctx.key_release(slot)
+
+
+def test_empty_inputs(ctx):
+    r = workloads.rng_for(31)
+    key, iv = workloads.random_bytes(r, 16).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    empty = torch.empty(0, dtype=torch.uint8, device="cuda")
+    tag = ctx.encrypt(key, iv, None, empty, empty)
+    assert tag == oracle.gcm_encrypt(key, iv, b"", b"")[1]
+    aad = workloads.random_bytes(r, 77)
+    tag = ctx.encrypt(key, iv, to_dev(aad), empty, empty)
+    assert tag == oracle.gcm_encrypt(key, iv, aad, b"")[1]
+    assert ctx.decrypt_verify(key, iv, to_dev(aad), empty, tag, empty)
+
+
+def test_argument_errors(ctx):
+    buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.encrypt(bytes(20), bytes(12), None, buf, buf)
+    assert e.value.code == gcm.GCM_E_KEYLEN
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.encrypt(bytes(16), bytes(16), None, buf, buf)
+    assert e.value.code == gcm.GCM_E_IVLEN
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.encrypt(bytes(16), bytes(12), None, buf[1:33], buf[32:64])
+    assert e.value.code == gcm.GCM_E_ARG  # misaligned
+    big = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.encrypt(bytes(16), bytes(12), None, big[0:128], big[16:144])
+    assert e.value.code == gcm.GCM_E_ALIAS
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.key_release(63)
+    assert e.value.code == gcm.GCM_E_SLOT
