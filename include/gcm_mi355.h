@@ -135,9 +135,20 @@ int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, siz
 /* Launch shape of the fused tile kernel.  Results never depend on it (the
  * counter and GHASH exponents derive from block indices only); only speed
  * does.  log2_tile_blocks: blocks per wave tile (6..20, 0 = automatic);
- * waves_per_group: 4, 8 or 16 (0 = automatic); groups_per_cu: resident
+ * waves_per_group: 8 or 16 (0 = automatic); groups_per_cu: resident
  * workgroups per compute unit (0 = automatic). */
 int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group, uint32_t groups_per_cu);
+
+/* ---------------------------------------------------------------- measurement */
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the fused
+ * CTR+GHASH tile kernel is bracketed by a pair of HIP events recorded on the
+ * stream the kernel runs on (the paper's kernel-only timing scope). */
+int gcm_profile_enable(gcm_ctx *ctx, int enable);
+
+/* Waits for the recorded events, returns the number of timed tile-kernel
+ * launches and their summed duration in milliseconds, and resets both. */
+int gcm_profile_read(gcm_ctx *ctx, uint64_t *launches, double *tile_ms_total);
 
 #ifdef __cplusplus
 }

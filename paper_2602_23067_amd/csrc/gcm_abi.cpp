@@ -137,6 +137,14 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
     ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
     ctx_free(ctx, ctx->d_io, 256);
     ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+    for (auto &pr : ctx->prof_pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto &pr : ctx->prof_free) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     if (ctx->h_io)
         (void)hipHostFree(ctx->h_io);
     delete ctx;
@@ -150,8 +158,8 @@ extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t 
         return fail(GCM_E_ARG, "gcm_set_launch: NULL context");
     if (log2_tile_blocks && (log2_tile_blocks < 6 || log2_tile_blocks > 20))
         return fail(GCM_E_ARG, "gcm_set_launch: log2_tile_blocks must be 0 or 6..20");
-    if (waves_per_group && waves_per_group != 4 && waves_per_group != 8 && waves_per_group != 16)
-        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 4, 8 or 16");
+    if (waves_per_group && waves_per_group != 8 && waves_per_group != 16)
+        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 8 or 16");
     if (groups_per_cu > 64)
         return fail(GCM_E_ARG, "gcm_set_launch: groups_per_cu must be <= 64");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -243,7 +251,7 @@ static int cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, 
 
 void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc)
 {
-    const uint32_t w = ctx->cfg_waves ? ctx->cfg_waves : 8;
+    const uint32_t w = ctx->cfg_waves ? ctx->cfg_waves : 16;
     uint32_t g = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)w);
     *waves = w;
     *gpc = g;
@@ -314,7 +322,11 @@ int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t 
     uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_bytes_for(0, 1);
     const uint32_t items = d.groups;
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(items, (uint32_t)ctx->cu_count * gpc));
-    hipError_t e = launch_tiles((int)waves, nullptr, nullptr, items, &d, ctx->d_tables, partials, counters, grid, s);
+    hipError_t e = prof_begin(ctx, s);
+    if (e == hipSuccess)
+        e = launch_tiles((int)waves, nullptr, nullptr, items, &d, ctx->d_tables, partials, counters, grid, s);
+    if (e == hipSuccess)
+        e = prof_end(ctx, s);
     if (e == hipSuccess)
         e = launch_combine(nullptr, 1, &d, ctx->d_tables, ctx->d_tables + 256, partials, counters, s);
     if (e == hipSuccess && d.op == 1) {
@@ -479,4 +491,68 @@ extern "C" int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_l
                                   const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream)
 {
     return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream);
+}
+
+// ---------------------------------------------------------------- measurement
+
+hipError_t gcm::prof_begin(gcm_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->prof)
+        return hipSuccess;
+    std::pair<hipEvent_t, hipEvent_t> pr;
+    if (!ctx->prof_free.empty()) {
+        pr = ctx->prof_free.back();
+        ctx->prof_free.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&pr.first);
+        if (e != hipSuccess)
+            return e;
+        e = hipEventCreate(&pr.second);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(pr.first);
+            return e;
+        }
+    }
+    ctx->prof_pending.push_back(pr);
+    return hipEventRecord(pr.first, s);
+}
+
+hipError_t gcm::prof_end(gcm_ctx *ctx, hipStream_t s)
+{
+    if (!ctx->prof || ctx->prof_pending.empty())
+        return hipSuccess;
+    return hipEventRecord(ctx->prof_pending.back().second, s);
+}
+
+extern "C" int gcm_profile_enable(gcm_ctx *ctx, int enable)
+{
+    if (!ctx)
+        return fail(GCM_E_ARG, "gcm_profile_enable: NULL context");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->prof = enable != 0;
+    return GCM_OK;
+}
+
+extern "C" int gcm_profile_read(gcm_ctx *ctx, uint64_t *launches, double *tile_ms_total)
+{
+    if (!ctx || !launches || !tile_ms_total)
+        return fail(GCM_E_ARG, "gcm_profile_read: NULL argument");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    double total = 0.0;
+    uint64_t n = 0;
+    for (auto &pr : ctx->prof_pending) {
+        hipError_t e = hipEventSynchronize(pr.second);
+        float ms = 0.f;
+        if (e == hipSuccess)
+            e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        if (e != hipSuccess)
+            return fail_hip(e, "profile event");
+        total += ms;
+        ++n;
+        ctx->prof_free.push_back(pr);
+    }
+    ctx->prof_pending.clear();
+    *launches = n;
+    *tile_ms_total = total;
+    return GCM_OK;
 }

@@ -31,6 +31,10 @@ struct gcm_ctx {
     uint8_t *h_io = nullptr;  // pinned mirror
     // launch shape overrides (0 = automatic)
     uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0;
+    // tile-kernel timing (events recorded on the launch stream)
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
     std::mutex mu;
 };
 
@@ -53,6 +57,9 @@ void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_
 int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
 uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
 int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
+// bracket the next tile launch with events when profiling is on (caller holds ctx->mu)
+hipError_t prof_begin(gcm_ctx *ctx, hipStream_t s);
+hipError_t prof_end(gcm_ctx *ctx, hipStream_t s);
 
 // kernels (gcm_kernels.hip)
 hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s);

@@ -48,6 +48,39 @@ __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Read-only device data (key slots, descriptors, work lists) is read through
+// the constant address space so uniform reads become scalar loads into SGPRs.
+#define CONST_AS __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const CONST_AS T *cptr(const void *p)
+{
+    return (const CONST_AS T *)(p);
+}
+
+// whole-struct read through the constant address space (word by word)
+template <typename T>
+__device__ __forceinline__ T load_const(const void *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized struct expected");
+    T v;
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&v);
+    const CONST_AS uint32_t *src = cptr<uint32_t>(p);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i)
+        dst[i] = src[i];
+    return v;
+}
+
+// Payload buffers are addressed in the global address space so that their
+// loads and stores use the vector-memory counter only and never make an LDS
+// wait also wait for HBM.
+#define GLOBAL_AS __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ GLOBAL_AS T *gptr(uint64_t addr)
+{
+    return (GLOBAL_AS T *)(addr);
+}
+
 // ---------------------------------------------------------------- AES tables
 //
 // S-box from GF(2^8) antilog/log tables with generator 0x03 (FIPS-197 sec.
@@ -275,11 +308,16 @@ __global__ __launch_bounds__(256) void k_key_tables(uint8_t *slot)
 __device__ __forceinline__ u32x4 mul_tab4(u32x4 a, const u32x4 *__restrict__ tab)
 {
     u32x4 r0 = {0, 0, 0, 0}, r1 = {0, 0, 0, 0};
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll 1
+    for (int d = 0; d < 4; ++d) {
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const uint32_t byte = byte_of(a, k);
-        r0 ^= tab[(2 * k) * 16 + (byte >> 4)];
-        r1 ^= tab[(2 * k + 1) * 16 + (byte & 15)];
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t byte = (w[d] >> (8 * q)) & 0xffu;
+            const int k = 4 * d + q;
+            r0 ^= tab[(2 * k) * 16 + (byte >> 4)];
+            r1 ^= tab[(2 * k + 1) * 16 + (byte & 15)];
+        }
     }
     return r0 ^ r1;
 }
@@ -310,59 +348,115 @@ __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 
 // ---------------------------------------------------------------- fused tile kernel
 //
-// LDS: [0, 4 KiB) the four AES T-tables (so byte<<2 indexes them with an
-// immediate table offset), [4 KiB, 68 KiB) the byte-position GHASH table of
-// H^64 for the current key.
+// LDS layout (128 KiB, one workgroup per CU):
+//   [0, 64 KiB)        byte-position GHASH table of H^64 for the current key
+//                      (16 positions x 256 entries x 16 B): lookup k of a
+//                      block reads entry (k, byte k) with one b128 read whose
+//                      immediate offset is k*4096.
+//   [64 KiB, 128 KiB)  AES T-tables: entry e of table t, copy c (c = 0..15)
+//                      at 0x10000 + 256*e + 64*t + 4*c.
+//
+// gfx950 LDS has 32 four-byte banks and resolves a wave64 access over all 64
+// lanes, so random indices into one 1 KiB table cost about three times the
+// conflict-free two cycles.  Here the bank of a T-table read depends only on
+// (t, c): lane l uses copy c = l & 15, and lane group g = (l >> 4) & 3 keeps
+// its AES state rotated left by 8g bits.  Because T_t = rotl(T_0, 8t), a
+// rotated state turns "table r, byte r" into "table (r+g)&3, byte (r+g)&3",
+// so in every lookup instruction the four lane groups read four different
+// tables and each bank serves exactly two lanes.  One v_perm_b32 per lookup
+// builds the address 0x10000 | byte << 8 | (64*table + 4*copy).
 
-constexpr int kLdsTeWords = 1024;
-constexpr int kLdsVec = 256 + 4096;  // u32x4 units
+constexpr uint32_t kTeBase = 0x10000u;
 
-struct AesCtx {
-    const uint32_t *te;  // LDS
-    uint32_t u0, u1, u2, u3;  // round-1 columns with the 12 IV bytes folded in
-    uint32_t rk3;             // round key 0, column 3
+struct LaneK {
+    uint32_t sel[4];   // v_perm selectors: byte u_r of the state word into bits 8..15
+    uint32_t off[4];   // 0x10000 | 64*u_r + 4*copy            (rounds 1..Nr-1)
+    uint32_t offl[4];  // 0x10000 | 64*((u_r+2)&3) + 4*copy    (last round)
+    uint32_t mask[4];  // 0xff << 8*u_r                         (last round)
+    uint32_t rot;      // alignbit shift for rotl by 8g
+    uint32_t unrot;    // alignbit shift for rotr by 8g
 };
 
-#define TE(r, x) te[(r) * 256 + (x)]
+__device__ __forceinline__ LaneK lane_constants(int lane)
+{
+    LaneK k;
+    const uint32_t g = (uint32_t)(lane >> 4) & 3u, copy = (uint32_t)lane & 15u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint32_t u = ((uint32_t)r + g) & 3u;
+        k.sel[r] = 0x0c020000u | ((4u + u) << 8);
+        k.off[r] = kTeBase | (u * 64u + copy * 4u);
+        k.offl[r] = kTeBase | (((u + 2u) & 3u) * 64u + copy * 4u);
+        k.mask[r] = 0xffu << (8u * u);
+    }
+    k.rot = (32u - 8u * g) & 31u;
+    k.unrot = 8u * g;
+    return k;
+}
+
+__device__ __forceinline__ uint32_t lds_word(const uint8_t *lds, uint32_t byte_addr)
+{
+    return *reinterpret_cast<const uint32_t *>(lds + byte_addr);
+}
+
+__device__ __forceinline__ uint32_t rotr_by(uint32_t x, uint32_t n) { return __builtin_amdgcn_alignbit(x, x, n); }
+
 #define B0(x) ((x) & 0xffu)
 #define B1(x) (((x) >> 8) & 0xffu)
 #define B2(x) (((x) >> 16) & 0xffu)
 #define B3(x) ((x) >> 24)
 
+// unrotated T_t[x] (uniform reads, used for the per-tile round-1 constants)
+__device__ __forceinline__ uint32_t te_u(const uint8_t *lds, uint32_t t, uint32_t x)
+{
+    return lds_word(lds, kTeBase + x * 256u + t * 64u);
+}
+
+// bits of a where m is set, bits of b elsewhere
+__device__ __forceinline__ uint32_t bsel(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
+
+#define LK(r, w) lds_word(lds, __builtin_amdgcn_perm((w), lk.off[r], lk.sel[r]))
+#define LL(r, w) lds_word(lds, __builtin_amdgcn_perm((w), lk.offl[r], lk.sel[r]))
+
+struct AesCtx {
+    uint32_t u0, u1, u2, u3;  // round-1 columns with the 12 IV bytes folded in (unrotated, uniform)
+    uint32_t rk3;             // round key 0, column 3
+};
+
 // Keystream block for counter value `ctr` (big-endian in bytes 12..15).
 // Only column 3 of the counter block varies, so round 1 needs four table
 // lookups instead of sixteen (counter-mode caching).
 template <int NR>
-__device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const uint32_t *__restrict__ rk)
+__device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const CONST_AS uint32_t *rk,
+                                         const uint8_t *lds, const LaneK &lk)
 {
-    const uint32_t *te = c.te;
     const uint32_t v = bswap32(ctr) ^ c.rk3;
-    uint32_t s0 = c.u0 ^ TE(3, B3(v));
-    uint32_t s1 = c.u1 ^ TE(2, B2(v));
-    uint32_t s2 = c.u2 ^ TE(1, B1(v));
-    uint32_t s3 = c.u3 ^ TE(0, B0(v));
+    const uint32_t w3 = rotr_by(v, lk.rot);  // rotl(v, 8g)
+    uint32_t s0 = rotr_by(c.u0, lk.rot) ^ LK(3, w3);
+    uint32_t s1 = rotr_by(c.u1, lk.rot) ^ LK(2, w3);
+    uint32_t s2 = rotr_by(c.u2, lk.rot) ^ LK(1, w3);
+    uint32_t s3 = rotr_by(c.u3, lk.rot) ^ LK(0, w3);
 #pragma unroll
     for (int r = 2; r < NR; ++r) {
-        const uint32_t t0 = xor3(xor3(TE(0, B0(s0)), TE(1, B1(s1)), TE(2, B2(s2))), TE(3, B3(s3)), rk[4 * r + 0]);
-        const uint32_t t1 = xor3(xor3(TE(0, B0(s1)), TE(1, B1(s2)), TE(2, B2(s3))), TE(3, B3(s0)), rk[4 * r + 1]);
-        const uint32_t t2 = xor3(xor3(TE(0, B0(s2)), TE(1, B1(s3)), TE(2, B2(s0))), TE(3, B3(s1)), rk[4 * r + 2]);
-        const uint32_t t3 = xor3(xor3(TE(0, B0(s3)), TE(1, B1(s0)), TE(2, B2(s1))), TE(3, B3(s2)), rk[4 * r + 3]);
+        const uint32_t k0 = rotr_by(rk[4 * r + 0], lk.rot), k1 = rotr_by(rk[4 * r + 1], lk.rot);
+        const uint32_t k2 = rotr_by(rk[4 * r + 2], lk.rot), k3 = rotr_by(rk[4 * r + 3], lk.rot);
+        const uint32_t t0 = xor3(xor3(LK(0, s0), LK(1, s1), LK(2, s2)), LK(3, s3), k0);
+        const uint32_t t1 = xor3(xor3(LK(0, s1), LK(1, s2), LK(2, s3)), LK(3, s0), k1);
+        const uint32_t t2 = xor3(xor3(LK(0, s2), LK(1, s3), LK(2, s0)), LK(3, s1), k2);
+        const uint32_t t3 = xor3(xor3(LK(0, s3), LK(1, s0), LK(2, s1)), LK(3, s2), k3);
         s0 = t0;
         s1 = t1;
         s2 = t2;
         s3 = t3;
     }
-    // last round: S-box only; TE2 holds S(x) in byte 0, TE3 in byte 1, TE0 in byte 2, TE1 in byte 3
-    u32x4 o;
-    o.x = ((TE(2, B0(s0)) & 0x000000ffu) | (TE(3, B1(s1)) & 0x0000ff00u) | (TE(0, B2(s2)) & 0x00ff0000u) |
-           (TE(1, B3(s3)) & 0xff000000u)) ^ rk[4 * NR + 0];
-    o.y = ((TE(2, B0(s1)) & 0x000000ffu) | (TE(3, B1(s2)) & 0x0000ff00u) | (TE(0, B2(s3)) & 0x00ff0000u) |
-           (TE(1, B3(s0)) & 0xff000000u)) ^ rk[4 * NR + 1];
-    o.z = ((TE(2, B0(s2)) & 0x000000ffu) | (TE(3, B1(s3)) & 0x0000ff00u) | (TE(0, B2(s0)) & 0x00ff0000u) |
-           (TE(1, B3(s1)) & 0xff000000u)) ^ rk[4 * NR + 2];
-    o.w = ((TE(2, B0(s3)) & 0x000000ffu) | (TE(3, B1(s0)) & 0x0000ff00u) | (TE(0, B2(s1)) & 0x00ff0000u) |
-           (TE(1, B3(s2)) & 0xff000000u)) ^ rk[4 * NR + 3];
-    return o;
+    // last round: S-box bytes only; table (u+2)&3 holds S(x) in byte u
+    const uint32_t k0 = rotr_by(rk[4 * NR + 0], lk.rot), k1 = rotr_by(rk[4 * NR + 1], lk.rot);
+    const uint32_t k2 = rotr_by(rk[4 * NR + 2], lk.rot), k3 = rotr_by(rk[4 * NR + 3], lk.rot);
+    const uint32_t o0 = bsel(lk.mask[0], LL(0, s0), bsel(lk.mask[1], LL(1, s1), bsel(lk.mask[2], LL(2, s2), LL(3, s3)))) ^ k0;
+    const uint32_t o1 = bsel(lk.mask[0], LL(0, s1), bsel(lk.mask[1], LL(1, s2), bsel(lk.mask[2], LL(2, s3), LL(3, s0)))) ^ k1;
+    const uint32_t o2 = bsel(lk.mask[0], LL(0, s2), bsel(lk.mask[1], LL(1, s3), bsel(lk.mask[2], LL(2, s0), LL(3, s1)))) ^ k2;
+    const uint32_t o3 = bsel(lk.mask[0], LL(0, s3), bsel(lk.mask[1], LL(1, s0), bsel(lk.mask[2], LL(2, s1), LL(3, s2)))) ^ k3;
+    return u32x4{rotr_by(o0, lk.unrot), rotr_by(o1, lk.unrot), rotr_by(o2, lk.unrot), rotr_by(o3, lk.unrot)};
 }
 
 // a * H^64 with the byte-position table in LDS (16 lookups of 16 bytes)
@@ -386,10 +480,21 @@ __device__ __forceinline__ u32x4 load_block_partial(const uint8_t *p, uint64_t b
     const uint64_t off = blk * 16;
     if (off + 16 <= total)
         return *reinterpret_cast<const u32x4 *>(p + off);
-    uint32_t w[4] = {0, 0, 0, 0};
-    for (uint64_t k = off; k < total; ++k)
-        w[(k - off) >> 2] |= (uint32_t)p[k] << (8 * ((k - off) & 3));
-    return u32x4{w[0], w[1], w[2], w[3]};
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    for (uint64_t k = off; k < total; ++k) {
+        const uint32_t b = (uint32_t)p[k] << (8 * ((k - off) & 3));
+        const uint64_t d = (k - off) >> 2;
+        w0 |= d == 0 ? b : 0u;
+        w1 |= d == 1 ? b : 0u;
+        w2 |= d == 2 ? b : 0u;
+        w3 |= d == 3 ? b : 0u;
+    }
+    return u32x4{w0, w1, w2, w3};
+}
+
+__device__ __forceinline__ uint32_t keep_bytes(uint32_t w, int nb)  // keep the low nb bytes (nb may be <=0 or >=4)
+{
+    return nb <= 0 ? 0u : nb >= 4 ? w : (w & ((1u << (8 * nb)) - 1u));
 }
 
 __device__ __forceinline__ u32x4 mask_block(u32x4 v, uint64_t blk, uint64_t total)
@@ -397,16 +502,8 @@ __device__ __forceinline__ u32x4 mask_block(u32x4 v, uint64_t blk, uint64_t tota
     const uint64_t off = blk * 16;
     if (off + 16 <= total)
         return v;
-    const uint32_t nb = (uint32_t)(total - off);  // 1..15 valid bytes
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    for (int d = 0; d < 4; ++d) {
-        const int lo = 4 * d;
-        if ((int)nb <= lo)
-            w[d] = 0;
-        else if ((int)nb < lo + 4)
-            w[d] &= (1u << (8 * (nb - lo))) - 1u;
-    }
-    return u32x4{w[0], w[1], w[2], w[3]};
+    const int nb = (int)(total - off);  // 1..15 valid bytes
+    return u32x4{keep_bytes(v.x, nb), keep_bytes(v.y, nb - 4), keep_bytes(v.z, nb - 8), keep_bytes(v.w, nb - 12)};
 }
 
 __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, uint64_t total, u32x4 v)
@@ -416,31 +513,33 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
         *reinterpret_cast<u32x4 *>(p + off) = v;
         return;
     }
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    for (uint64_t k = off; k < total; ++k)
-        p[k] = (uint8_t)(w[(k - off) >> 2] >> (8 * ((k - off) & 3)));
+    for (uint64_t k = off; k < total; ++k) {
+        const uint64_t d = (k - off) >> 2;
+        const uint32_t w = d == 0 ? v.x : d == 1 ? v.y : d == 2 ? v.z : v.w;
+        p[k] = (uint8_t)(w >> (8 * ((k - off) & 3)));
+    }
 }
 
 // One wave processes wave tile t of message d: rows of 64 consecutive
 // blocks, lane l on block 64*r + l, so every load/store instruction moves one
 // contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
-// p_t = sum_l a_l * H^(63-l) is formed by squaring-style fix-ups and an XOR
+// p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
 // across the wave.
 template <int NR>
-__device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint32_t *__restrict__ te,
-                          const u32x4 *__restrict__ tab8, u32x4 *__restrict__ partials)
+__device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
+                          u32x4 *__restrict__ partials)
 {
     const int lane = threadIdx.x & 63;
-    const uint32_t *__restrict__ rk = reinterpret_cast<const KeySlotHdr *>(d.slot)->rk;
-
+    const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
+    const CONST_AS uint32_t *rk = rk_base;
+    const u32x4 *tab8 = reinterpret_cast<const u32x4 *>(lds);
     AesCtx c;
-    c.te = te;
     {
         const uint32_t s0 = d.iv[0] ^ rk[0], s1 = d.iv[1] ^ rk[1], s2 = d.iv[2] ^ rk[2];
-        c.u0 = uniform(TE(0, B0(s0)) ^ TE(1, B1(s1)) ^ TE(2, B2(s2)) ^ rk[4]);
-        c.u1 = uniform(TE(0, B0(s1)) ^ TE(1, B1(s2)) ^ TE(3, B3(s0)) ^ rk[5]);
-        c.u2 = uniform(TE(0, B0(s2)) ^ TE(2, B2(s0)) ^ TE(3, B3(s1)) ^ rk[6]);
-        c.u3 = uniform(TE(1, B1(s0)) ^ TE(2, B2(s1)) ^ TE(3, B3(s2)) ^ rk[7]);
+        c.u0 = uniform(te_u(lds, 0, B0(s0)) ^ te_u(lds, 1, B1(s1)) ^ te_u(lds, 2, B2(s2)) ^ rk[4]);
+        c.u1 = uniform(te_u(lds, 0, B0(s1)) ^ te_u(lds, 1, B1(s2)) ^ te_u(lds, 3, B3(s0)) ^ rk[5]);
+        c.u2 = uniform(te_u(lds, 0, B0(s2)) ^ te_u(lds, 2, B2(s0)) ^ te_u(lds, 3, B3(s1)) ^ rk[6]);
+        c.u3 = uniform(te_u(lds, 1, B1(s0)) ^ te_u(lds, 2, B2(s1)) ^ te_u(lds, 3, B3(s2)) ^ rk[7]);
         c.rk3 = rk[3];
     }
 
@@ -454,23 +553,29 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint32_t *__restri
     const bool enc = d.op == 0;
     const uint8_t *__restrict__ in = reinterpret_cast<const uint8_t *>(d.in);
     uint8_t *__restrict__ out = reinterpret_cast<uint8_t *>(d.out);
+    const GLOBAL_AS u32x4 *in_g = gptr<const u32x4>(d.in);
+    GLOBAL_AS u32x4 *out_g = gptr<u32x4>(d.out);
 
     u32x4 a = {0, 0, 0, 0};
     for (uint32_t r = r0; r < R; ++r) {
+        // re-read the round keys with scalar loads each row instead of holding
+        // 4*(Nr+1) of them (or their lane-rotated copies) in registers
+        rk = rk_base;
+        asm volatile("" : "+s"(rk));
         const int64_t v0 = vbase + 64 * (int64_t)r;
         if (v0 >= na && v0 + 64 <= na + nfull) {
             // all 64 lanes hold whole data blocks
             const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
-            const u32x4 x = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(in) + j);
-            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk);
+            const u32x4 x = __builtin_nontemporal_load(in_g + j);
+            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
             const u32x4 o = x ^ ks;
-            __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(out) + j);
+            __builtin_nontemporal_store(o, out_g + j);
             a = ghash_mul8(a, tab8) ^ (enc ? o : x);
         } else {
             // boundary row: zero padding, AAD, partial blocks or the length block
             const int64_t v = v0 + lane;
             const uint64_t j = (uint64_t)(v - na);
-            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk);
+            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
             u32x4 X = {0, 0, 0, 0};
             if (v >= 0 && v < na) {
                 X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
@@ -495,28 +600,25 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint32_t *__restri
         partials[d.tile_base + t] = a;
 }
 
-template <int NR>
-__device__ __forceinline__ void wave_tile_dispatch(const MsgDesc &d, uint64_t t, const uint32_t *te, const u32x4 *tab8,
-                                                   u32x4 *partials)
-{
-    wave_tile<NR>(d, t, te, tab8, partials);
-}
-
 template <int WAVES, bool BATCH>
 __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restrict__ descs,
                                                           const WorkItem *__restrict__ items, uint32_t n_items,
                                                           MsgDesc single, const uint32_t *__restrict__ te0g,
                                                           u32x4 *__restrict__ partials, uint32_t *counters)
 {
-    __shared__ u32x4 lds[kLdsVec];
-    uint32_t *te = reinterpret_cast<uint32_t *>(lds);
-    u32x4 *tab8 = lds + 256;
+    __shared__ u32x4 lds_v[8192];  // 128 KiB: GHASH table, then the replicated T-tables
+    const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
 
     if (blockIdx.x == 0 && threadIdx.x == 0)
         counters[0] = 0;  // reject count for this launch (read by the zero-fill)
 
-    for (int i = threadIdx.x; i < kLdsTeWords; i += WAVES * 64)
-        te[i] = rotl32(te0g[i & 255], 8 * (i >> 8));
+    {
+        // T-tables: dword 16384 + 64*e + 16*t + c holds rotl(TE0[e], 8t)
+        uint32_t *w = reinterpret_cast<uint32_t *>(lds_v) + 16384;
+        for (int i = threadIdx.x; i < 16384; i += WAVES * 64)
+            w[i] = rotl32(te0g[i >> 6], 8 * ((i >> 4) & 3));
+    }
+    const LaneK lk = lane_constants(threadIdx.x & 63);
 
     uint64_t cur_slot = 0;
     const int wave = threadIdx.x >> 6;
@@ -524,8 +626,8 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         MsgDesc d;
         uint32_t first;
         if (BATCH) {
-            const WorkItem w = items[it];
-            d = descs[w.msg];
+            const WorkItem w = load_const<WorkItem>(items + it);
+            d = load_const<MsgDesc>(descs + w.msg);
             first = w.first_tile;
         } else {
             d = single;
@@ -535,18 +637,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             __syncthreads();
             const u32x4 *src = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab8Off);
             for (int i = threadIdx.x; i < 4096; i += WAVES * 64)
-                tab8[i] = src[i];
+                lds_v[i] = src[i];
             cur_slot = d.slot;
             __syncthreads();
         }
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.n_tiles) {
             if (d.nr == 10)
-                wave_tile_dispatch<10>(d, t, te, tab8, partials);
+                wave_tile<10>(d, t, lds, lk, partials);
             else if (d.nr == 12)
-                wave_tile_dispatch<12>(d, t, te, tab8, partials);
+                wave_tile<12>(d, t, lds, lk, partials);
             else
-                wave_tile_dispatch<14>(d, t, te, tab8, partials);
+                wave_tile<14>(d, t, lds, lk, partials);
         }
     }
 }
@@ -679,8 +781,6 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
 {
     u32x4 *p = reinterpret_cast<u32x4 *>(partials);
     switch (waves) {
-    case 4:
-        return launch_tiles_w<4>(descs, items, n_items, single, te0, p, counters, grid, s);
     case 8:
         return launch_tiles_w<8>(descs, items, n_items, single, te0, p, counters, grid, s);
     case 16:
@@ -695,9 +795,6 @@ int max_groups_per_cu(int waves)
     int n = 0;
     hipError_t e = hipErrorInvalidValue;
     switch (waves) {
-    case 4:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<4, false>, 4 * 64, 0);
-        break;
     case 8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false>, 8 * 64, 0);
         break;

@@ -56,6 +56,8 @@ def load() -> ctypes.CDLL:
         "gcm_encrypt_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, u64, vp], ctypes.c_int),
         "gcm_decrypt_verify_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, vp, u64, vp], ctypes.c_int),
         "gcm_set_launch": ([vp, u32, u32, u32], ctypes.c_int),
+        "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
+        "gcm_profile_read": ([vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -170,6 +172,17 @@ class Context:
                                                0 if aad is None else aad.numel(), _dev(ct), ct.numel(),
                                                _dev(tag_d), _dev(pt), accept_d.data_ptr(), _dev(workspace),
                                                workspace.numel(), _stream(stream)))
+
+    # -------------------------------------------------------- measurement
+    def profile_enable(self, on: bool = True) -> None:
+        _check(load().gcm_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self):
+        """(tile-kernel launches, summed tile-kernel milliseconds) since the last read."""
+        n = ctypes.c_uint64()
+        ms = ctypes.c_double()
+        _check(load().gcm_profile_read(self._h, ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
 
     # -------------------------------------------------------- tuning
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
