@@ -83,6 +83,13 @@ const char *gcm_last_error(void);
  * GCM_E_BUSY if every slot is taken. */
 int gcm_key_register(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, void *stream);
 
+/* Register n keys with as few launches as possible (the paper's H-power
+ * precompute for a whole batch of keys).  keys: the n keys concatenated
+ * (host); key_lens[i]: 16, 24 or 32; slots_out[i] receives key i's slot.
+ * Either every key gets a slot or none does (GCM_E_BUSY). */
+int gcm_key_register_many(gcm_ctx *ctx, const uint8_t *keys, const uint32_t *key_lens, uint32_t n,
+                          uint32_t *slots_out, void *stream);
+
 /* Return a slot to the free list.  The caller guarantees no queued work
  * still uses it. */
 int gcm_key_release(gcm_ctx *ctx, uint32_t slot);
@@ -129,6 +136,52 @@ int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, siz
                              const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
                              const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
                              uint64_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- batches */
+
+/* One message of a batch.  All offsets are byte offsets into one device
+ * allocation `base_d` (256-byte aligned) of `base_bytes` bytes. */
+typedef struct gcm_job {
+    uint32_t op;        /* 0 = encrypt, 1 = decrypt-verify */
+    uint32_t key_slot;  /* a registered key slot */
+    uint8_t iv[12];     /* 96-bit IV */
+    uint32_t reserved;  /* must be 0 */
+    uint64_t aad_off;   /* AAD (16-byte aligned offset) */
+    uint64_t aad_len;
+    uint64_t in_off;    /* input payload (16-byte aligned) */
+    uint64_t out_off;   /* output payload (16-byte aligned; == in_off for in place) */
+    uint64_t len;       /* payload bytes, any length */
+    uint64_t tag_off;   /* encrypt: tag written here; decrypt: expected tag read here */
+    uint64_t ok_off;    /* decrypt: int32 accept flag written here (4-byte aligned) */
+} gcm_job;
+
+typedef struct gcm_batch gcm_batch;
+
+/* Plan a batch: validates every job (bounds, alignment, aliasing, key slots),
+ * builds per-message descriptors, the tile prefix table and the work list of
+ * the persistent launch (the paper's map phase spread over many messages) and
+ * uploads them (blocking).  The plan binds base_d; jobs may be freed after. */
+int gcm_batch_create(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes,
+                     gcm_batch **out);
+
+/* Enqueue one pass over the batch on `stream`: the fused tile kernel over all
+ * messages in one persistent launch, the per-message combine (tags / accept
+ * flags written to base_d) and the zero-fill of rejected outputs.  Allocates
+ * nothing; results are identical to running each message alone. */
+int gcm_batch_launch(gcm_batch *b, void *stream);
+
+/* Same as gcm_batch_launch, but the kernels are captured once into a hipGraph
+ * (on a private stream) and every call replays the graph on `stream`. */
+int gcm_batch_graph_launch(gcm_batch *b, void *stream);
+
+/* Payload bytes, total wave tiles and workgroup items of a plan (any may be NULL). */
+int gcm_batch_info(const gcm_batch *b, uint64_t *payload_bytes, uint64_t *total_tiles, uint32_t *work_items);
+
+/* Wait for the device, then free the plan's device tables and graph. */
+int gcm_batch_destroy(gcm_batch *b);
+
+/* Convenience: create, launch, synchronise `stream`, destroy. */
+int gcm_batch_run(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes, void *stream);
 
 /* ---------------------------------------------------------------- tuning */
 

@@ -171,27 +171,36 @@ extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t 
 
 // ---------------------------------------------------------------- keys
 
-int gcm::register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, hipStream_t s)
+int gcm::register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_t *key_lens, uint32_t n,
+                              uint32_t *slots_out, hipStream_t s)
 {
-    uint32_t slot = ctx->n_slots;
-    for (uint32_t i = 0; i < ctx->n_slots; ++i) {
-        if (!ctx->slot_used[i]) {
-            slot = i;
-            break;
-        }
-    }
-    if (slot == ctx->n_slots)
-        return fail(GCM_E_BUSY, "no free key slot (%u slots)", ctx->n_slots);
+    std::vector<uint32_t> picked;
+    picked.reserve(n);
+    for (uint32_t i = 0; i < ctx->n_slots && picked.size() < n; ++i)
+        if (!ctx->slot_used[i])
+            picked.push_back(i);
+    if (picked.size() < n)
+        return fail(GCM_E_BUSY, "%u key slots requested, %zu free (%u slots)", n, picked.size(), ctx->n_slots);
+    std::vector<uint64_t> addrs(n);
+    for (uint32_t i = 0; i < n; ++i)
+        addrs[i] = (uint64_t)(ctx->d_slots + kSlotBytes * picked[i]);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = launch_key_setup(key, (uint32_t)key_len, ctx->d_slots + kSlotBytes * slot, ctx->d_tables,
-                             ctx->d_tables + 256, s);
+        e = launch_key_setup(keys, key_lens, addrs.data(), n, ctx->d_tables, ctx->d_tables + 256, s);
     if (e != hipSuccess)
         return fail_hip(e, "key setup launch");
-    ctx->slot_used[slot] = 1;
-    ctx->slot_nr[slot] = (uint32_t)(key_len / 4 + 6);
-    *slot_out = slot;
+    for (uint32_t i = 0; i < n; ++i) {
+        ctx->slot_used[picked[i]] = 1;
+        ctx->slot_nr[picked[i]] = key_lens[i] / 4 + 6;
+        slots_out[i] = picked[i];
+    }
     return GCM_OK;
+}
+
+int gcm::register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, hipStream_t s)
+{
+    const uint32_t len = (uint32_t)key_len;
+    return register_keys_locked(ctx, &key, &len, 1, slot_out, s);
 }
 
 static bool valid_key_len(size_t n) { return n == 16 || n == 24 || n == 32; }
@@ -204,6 +213,23 @@ extern "C" int gcm_key_register(gcm_ctx *ctx, const uint8_t *key, size_t key_len
         return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
     std::lock_guard<std::mutex> g(ctx->mu);
     return register_key_locked(ctx, key, key_len, slot_out, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int gcm_key_register_many(gcm_ctx *ctx, const uint8_t *keys, const uint32_t *key_lens, uint32_t n,
+                                     uint32_t *slots_out, void *stream)
+{
+    if (!ctx || (n && (!keys || !key_lens || !slots_out)))
+        return fail(GCM_E_ARG, "gcm_key_register_many: NULL argument");
+    std::vector<const uint8_t *> ptrs(n);
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!valid_key_len(key_lens[i]))
+            return fail(GCM_E_KEYLEN, "key %u: length %u is not 16, 24 or 32", i, key_lens[i]);
+        ptrs[i] = keys + off;
+        off += key_lens[i];
+    }
+    std::lock_guard<std::mutex> g(ctx->mu);
+    return register_keys_locked(ctx, ptrs.data(), key_lens, n, slots_out, reinterpret_cast<hipStream_t>(stream));
 }
 
 extern "C" int gcm_key_release(gcm_ctx *ctx, uint32_t slot)

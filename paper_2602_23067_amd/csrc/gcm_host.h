@@ -49,6 +49,8 @@ int fail_hip(hipError_t e, const char *what);
 int ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes);
 void ctx_free(gcm_ctx *ctx, void *p, uint64_t bytes);
 int register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, hipStream_t s);
+int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_t *key_lens, uint32_t n,
+                         uint32_t *slots_out, hipStream_t s);
 
 void launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc);
 void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in, uint64_t out,
@@ -63,8 +65,8 @@ hipError_t prof_end(gcm_ctx *ctx, hipStream_t s);
 
 // kernels (gcm_kernels.hip)
 hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s);
-hipError_t launch_key_setup(const uint8_t *key, uint32_t key_len, uint8_t *slot, const uint32_t *te0,
-                            const uint32_t *sbox, hipStream_t s);
+hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens, const uint64_t *slot_addrs,
+                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, hipStream_t s);
 hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, uint32_t n_items,
                         const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
                         hipStream_t s);

@@ -20,6 +20,7 @@ constexpr int kMaxNr = 14;
 constexpr int kPowLevels = 48;      // H^(2^k), k = 0..47
 constexpr int kTab4Levels = 40;     // nibble tables for H^(2^k), k = 0..39
 constexpr int kStrideLevel = 6;     // the per-lane Horner multiplier is H^64 = H^(2^6)
+constexpr int kKeyChunk = 56;       // keys per key-setup launch (by-value kernel arguments)
 
 struct KeySlotHdr {
     uint32_t rk[4 * (kMaxNr + 1)];  // round keys, memory-order column words

@@ -155,6 +155,16 @@ struct KeyArg {
     uint32_t len;
 };
 
+// Keys travel to the device as by-value kernel arguments, in chunks that fit
+// the 4 KiB argument segment: no staging buffer, stream-ordered, capturable.
+struct KeyChunk {
+    KeyArg keys[kKeyChunk];
+    uint64_t slots[kKeyChunk];
+};
+struct SlotChunk {
+    uint64_t slots[kKeyChunk];
+};
+
 __device__ __forceinline__ uint32_t sub_word(uint32_t t, const uint32_t *sb)
 {
     return sb[t & 0xff] | (sb[(t >> 8) & 0xff] << 8) | (sb[(t >> 16) & 0xff] << 16) | (sb[t >> 24] << 24);
@@ -220,12 +230,21 @@ __device__ P128 poly_square(P128 a)
     return r;
 }
 
-// One thread: round keys, H = E_K(0^128), H^(2^k) by repeated squaring.
-__global__ void k_key_setup(KeyArg key, uint8_t *slot, const uint32_t *te0, const uint32_t *sb)
+// One workgroup per key (blockIdx.x indexes `keys`/`slots`): the AES tables
+// are staged in LDS, then one thread derives the round keys, H = E_K(0^128)
+// and H^(2^k) by repeated squaring.
+__global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t *te0g, const uint32_t *sbg)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0)
+    __shared__ uint32_t te0[256], sb[256];
+    for (int i = threadIdx.x; i < 256; i += 64) {
+        te0[i] = te0g[i];
+        sb[i] = sbg[i];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
         return;
-    KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(slot);
+    const KeyArg key = chunk.keys[blockIdx.x];
+    KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(chunk.slots[blockIdx.x]);
     const int nk = (int)key.len / 4, nr = nk + 6;
     uint32_t w[4 * (kMaxNr + 1)];
     for (int i = 0; i < nk; ++i)
@@ -264,9 +283,10 @@ __global__ void k_key_setup(KeyArg key, uint8_t *slot, const uint32_t *te0, cons
 // Fixed-multiplier tables.  Block b < kTab4Levels builds the nibble-position
 // table of H^(2^b); the last block builds the byte-position table of
 // H^(2^kStrideLevel) = H^64, the per-lane Horner multiplier of the tile kernel.
-__global__ __launch_bounds__(256) void k_key_tables(uint8_t *slot)
+__global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
 {
     __shared__ u32x4 basis[128];  // basis[i] = M * x^i, memory order
+    uint8_t *slot = reinterpret_cast<uint8_t *>(chunk.slots[blockIdx.y]);
     const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
     const int b = blockIdx.x;
     const int lvl = b < kTab4Levels ? b : kStrideLevel;
@@ -660,8 +680,10 @@ constexpr int kCombineLog2 = 10;
 
 // S = sum_t p_t * H^((T-1-t)*B + 1); tag = S xor E_K(J0).  Thread i runs a
 // Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B),
-// then lifts its value by H^((T-1-t_last)*B); the XOR over threads closes
-// the tree, and one more *H accounts for GHASH's final multiplication.
+// lifts its value by H^((T-1-t_last)*B) through the exponent bits, and the
+// XOR over threads closes the tree; one more *H accounts for GHASH's final
+// multiplication.  The nibble tables this needs (at most 12 of 8 KiB) are
+// staged in LDS first, so every multiply is 32 LDS reads.
 template <bool BATCH>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
                                                                  const uint32_t *__restrict__ te0g,
@@ -669,22 +691,49 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
 {
+    __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
     __shared__ u32x4 red[kCombineThreads / 64];
-    const MsgDesc d = BATCH ? descs[blockIdx.x] : single;
+    __shared__ uint32_t s_te0[256], s_sb[256];
+    const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
     const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
 
+    // exponent bits needed for T-1-t_last < min(T, 1024), and whether any
+    // thread owns more than one partial
+    const uint64_t span = T < (uint64_t)kCombineThreads ? T : (uint64_t)kCombineThreads;
+    int nbits = 0;
+    while (nbits < kCombineLog2 && (1ull << nbits) < span)
+        ++nbits;
+    const bool horner = T > (uint64_t)kCombineThreads;
+    {
+        const u32x4 *g = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off);
+        const int ntab = 1 + (horner ? kCombineLog2 + 1 : nbits);
+        for (int e = (int)i; e < ntab * 512; e += kCombineThreads) {
+            const int tix = e >> 9;
+            const int lvl = tix == 0 ? 0 : (int)d.log2B + tix - 1;
+            tabs[tix][e & 511] = g[(uint64_t)lvl * 512 + (e & 511)];
+        }
+        if (i < 256) {
+            s_te0[i] = te0g[i];
+            s_sb[i] = sbg[i];
+        }
+    }
+    __syncthreads();
+
     u32x4 acc = {0, 0, 0, 0};
     if (i < T) {
-        const u32x4 *tabS = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off +
-                                                            (uint64_t)(d.log2B + kCombineLog2) * kTab4Bytes);
-        uint64_t t = i, t_last = i;
-        for (; t < T; t += kCombineThreads) {
-            acc = mul_tab4(acc, tabS) ^ partials[d.tile_base + t];
+        uint64_t t_last = i;
+        for (uint64_t t = i; t < T; t += kCombineThreads) {
+            acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ partials[d.tile_base + t];
             t_last = t;
         }
-        acc = mul_hpow(acc, T - 1 - t_last, kCombineLog2, slot, (int)d.log2B);
+        const uint64_t e = T - 1 - t_last;
+        for (int k = 0; k < nbits; ++k) {
+            const u32x4 m = mul_tab4(acc, tabs[1 + k]);
+            if ((e >> k) & 1)
+                acc = m;
+        }
     }
     acc = wave_xor_reduce(acc);
     if ((i & 63) == 0)
@@ -694,18 +743,20 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         u32x4 s = red[0];
         for (int w = 1; w < kCombineThreads / 64; ++w)
             s ^= red[w];
-        s = mul_tab4(s, reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off));  // * H
+        s = mul_tab4(s, tabs[0]);  // * H
         const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
         const uint32_t j0[4] = {d.iv[0], d.iv[1], d.iv[2], 0x01000000u};
         uint32_t ek[4];
-        aes_block_global(hd->rk, (int)hd->nr, te0g, sbg, j0, ek);
+        aes_block_global(hd->rk, (int)hd->nr, s_te0, s_sb, j0, ek);
         const u32x4 tag = s ^ u32x4{ek[0], ek[1], ek[2], ek[3]};
+        const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         if (d.op == 0) {
-            *reinterpret_cast<u32x4 *>(d.tag) = tag;
+            uint8_t *dst = reinterpret_cast<uint8_t *>(d.tag);
+            for (int k = 0; k < 16; ++k)
+                dst[k] = (uint8_t)(tw[k >> 2] >> (8 * (k & 3)));
         } else {
             const uint8_t *exp = reinterpret_cast<const uint8_t *>(d.tag);
             uint32_t diff = 0;
-            const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
             for (int k = 0; k < 16; ++k)
                 diff |= ((tw[k >> 2] >> (8 * (k & 3))) & 0xffu) ^ exp[k];
             const int32_t ok = diff == 0 ? 1 : 0;
@@ -745,20 +796,35 @@ hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_key_setup(const uint8_t *key, uint32_t key_len, uint8_t *slot, const uint32_t *te0,
-                            const uint32_t *sbox, hipStream_t s)
+// Expand n keys (key i: key_lens[i] bytes at keys + key_off[i]) into the
+// slots at slot_addrs[i], in launches of kKeyChunk keys.
+hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens, const uint64_t *slot_addrs,
+                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, hipStream_t s)
 {
-    KeyArg ka{};
-    for (uint32_t i = 0; i < key_len / 4; ++i)
-        ka.w[i] = (uint32_t)key[4 * i] | ((uint32_t)key[4 * i + 1] << 8) | ((uint32_t)key[4 * i + 2] << 16) |
-                  ((uint32_t)key[4 * i + 3] << 24);
-    ka.len = key_len;
-    hipLaunchKernelGGL(k_key_setup, dim3(1), dim3(64), 0, s, ka, slot, te0, sbox);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1), dim3(256), 0, s, slot);
-    return hipGetLastError();
+    for (uint32_t base = 0; base < n; base += kKeyChunk) {
+        const uint32_t m = n - base < (uint32_t)kKeyChunk ? n - base : (uint32_t)kKeyChunk;
+        KeyChunk kc{};
+        SlotChunk sc{};
+        for (uint32_t j = 0; j < m; ++j) {
+            const uint8_t *key = keys[base + j];
+            const uint32_t len = key_lens[base + j];
+            for (uint32_t i = 0; i < len / 4; ++i)
+                kc.keys[j].w[i] = (uint32_t)key[4 * i] | ((uint32_t)key[4 * i + 1] << 8) |
+                                  ((uint32_t)key[4 * i + 2] << 16) | ((uint32_t)key[4 * i + 3] << 24);
+            kc.keys[j].len = len;
+            kc.slots[j] = slot_addrs[base + j];
+            sc.slots[j] = slot_addrs[base + j];
+        }
+        hipLaunchKernelGGL(k_key_setup, dim3(m), dim3(64), 0, s, kc, te0, sbox);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1, m), dim3(256), 0, s, sc);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
 }
 
 template <int WAVES>

@@ -28,6 +28,24 @@ GCM_E_SLOT = -9
 _lib: Optional[ctypes.CDLL] = None
 
 
+class Job(ctypes.Structure):
+    """Mirror of ``gcm_job`` (include/gcm_mi355.h)."""
+
+    _fields_ = [
+        ("op", ctypes.c_uint32),
+        ("key_slot", ctypes.c_uint32),
+        ("iv", ctypes.c_uint8 * 12),
+        ("reserved", ctypes.c_uint32),
+        ("aad_off", ctypes.c_uint64),
+        ("aad_len", ctypes.c_uint64),
+        ("in_off", ctypes.c_uint64),
+        ("out_off", ctypes.c_uint64),
+        ("len", ctypes.c_uint64),
+        ("tag_off", ctypes.c_uint64),
+        ("ok_off", ctypes.c_uint64),
+    ]
+
+
 class GcmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -56,6 +74,13 @@ def load() -> ctypes.CDLL:
         "gcm_encrypt_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, u64, vp], ctypes.c_int),
         "gcm_decrypt_verify_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, vp, u64, vp], ctypes.c_int),
         "gcm_set_launch": ([vp, u32, u32, u32], ctypes.c_int),
+        "gcm_key_register_many": ([vp, vp, vp, u32, vp, vp], ctypes.c_int),
+        "gcm_batch_create": ([vp, vp, u32, vp, u64, ctypes.POINTER(vp)], ctypes.c_int),
+        "gcm_batch_launch": ([vp, vp], ctypes.c_int),
+        "gcm_batch_graph_launch": ([vp, vp], ctypes.c_int),
+        "gcm_batch_info": ([vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32)], ctypes.c_int),
+        "gcm_batch_destroy": ([vp], ctypes.c_int),
+        "gcm_batch_run": ([vp, vp, u32, vp, u64, vp], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "gcm_profile_read": ([vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -139,6 +164,17 @@ class Context:
         _check(load().gcm_key_register(self._h, _host(key), len(key), ctypes.byref(slot), _stream(stream)))
         return slot.value
 
+    def key_register_many(self, keys, stream=None):
+        """Register a list of keys in as few launches as possible; returns slots."""
+        import numpy as np
+
+        lens = np.asarray([len(k) for k in keys], dtype=np.uint32)
+        blob = b"".join(bytes(k) for k in keys)
+        slots = np.zeros(len(keys), dtype=np.uint32)
+        _check(load().gcm_key_register_many(self._h, _host(blob) if blob else None, lens.ctypes.data,
+                                            len(keys), slots.ctypes.data, _stream(stream)))
+        return [int(x) for x in slots]
+
     def key_release(self, slot: int) -> None:
         _check(load().gcm_key_release(self._h, slot))
 
@@ -187,3 +223,91 @@ class Context:
     # -------------------------------------------------------- tuning
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
         _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))
+
+
+# ------------------------------------------------------------------ batches
+
+def align_up(x: int, a: int = 256) -> int:
+    return (x + a - 1) // a * a
+
+
+class BatchLayout:
+    """Byte offsets of a packed batch inside one device buffer.
+
+    Each message gets its AAD, input and output (or input only when in
+    place) at 256-byte aligned offsets; the 16-byte tags and 4-byte accept
+    flags sit in two arrays after the payloads.  Only offsets are computed
+    here; callers fill the buffer."""
+
+    def __init__(self, lengths, aad_lens, in_place: bool = False):
+        self.n = len(lengths)
+        self.aad_off, self.in_off, self.out_off = [], [], []
+        off = 0
+        for ln, al in zip(lengths, aad_lens):
+            self.aad_off.append(off)
+            off = align_up(off + int(al))
+            self.in_off.append(off)
+            off = align_up(off + int(ln))
+            if in_place:
+                self.out_off.append(self.in_off[-1])
+            else:
+                self.out_off.append(off)
+                off = align_up(off + int(ln))
+        self.tag_base = off
+        off = align_up(off + 16 * self.n)
+        self.ok_base = off
+        off = align_up(off + 4 * self.n)
+        self.total = max(off, 256)
+        self.lengths = [int(x) for x in lengths]
+        self.aad_lens = [int(x) for x in aad_lens]
+
+    def jobs(self, ops, slots, ivs):
+        arr = (Job * self.n)()
+        for i in range(self.n):
+            j = arr[i]
+            j.op = int(ops[i])
+            j.key_slot = int(slots[i])
+            j.iv[:] = list(bytes(ivs[i]))
+            j.reserved = 0
+            j.aad_off = self.aad_off[i]
+            j.aad_len = self.aad_lens[i]
+            j.in_off = self.in_off[i]
+            j.out_off = self.out_off[i]
+            j.len = self.lengths[i]
+            j.tag_off = self.tag_base + 16 * i
+            j.ok_off = self.ok_base + 4 * i
+        return arr
+
+
+class Batch:
+    """A planned batch bound to one device buffer (see gcm_batch_create)."""
+
+    def __init__(self, ctx: Context, jobs, base):
+        self._ctx = ctx
+        self._base = base  # keep the buffer alive
+        h = ctypes.c_void_p()
+        _check(load().gcm_batch_create(ctx.handle, ctypes.cast(jobs, ctypes.c_void_p), len(jobs), _dev(base),
+                                       base.numel(), ctypes.byref(h)))
+        self._h = h
+
+    def launch(self, stream=None) -> None:
+        _check(load().gcm_batch_launch(self._h, _stream(stream)))
+
+    def graph_launch(self, stream=None) -> None:
+        _check(load().gcm_batch_graph_launch(self._h, _stream(stream)))
+
+    def info(self):
+        pb, tt, wi = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint32()
+        _check(load().gcm_batch_info(self._h, ctypes.byref(pb), ctypes.byref(tt), ctypes.byref(wi)))
+        return {"payload_bytes": pb.value, "total_tiles": tt.value, "work_items": wi.value}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().gcm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
