@@ -41,6 +41,11 @@ def parse():
     ap.add_argument("--log2-tile", type=int, default=0)
     ap.add_argument("--waves", type=int, default=0)
     ap.add_argument("--gpc", type=int, default=0)
+    ap.add_argument("--skip-batch", action="store_true", help="skip the 4096-message batch (config 3)")
+    ap.add_argument("--skip-dec-batch", action="store_true", help="skip the 1024 x 64 MiB decrypt batch (config 4)")
+    ap.add_argument("--batch-msgs", type=int, default=4096)
+    ap.add_argument("--dec-files", type=int, default=1024)
+    ap.add_argument("--dec-side", type=int, default=4096)
     return ap.parse_args()
 
 
@@ -53,6 +58,154 @@ def cpu_model() -> str:
     except OSError:
         pass
     return platform.processor() or "unknown"
+
+
+def run_batch_config3(ctx, gcm, workloads, torch, n_msgs, steps):
+    """Config 3: n_msgs lognormal messages (median 1 MiB, 4 KiB..64 MiB), per
+    message AES-128/256 key, IV and 0..4 KiB AAD, in one persistent launch;
+    compared with one launch sequence per message on the same GPU."""
+    import numpy as np
+
+    spec = workloads.config3_spec(n_msgs=n_msgs)
+    lay = gcm.BatchLayout(spec.lengths, spec.aad_lens)
+    dev = torch.device("cuda:0")
+    base = torch.empty(lay.total, dtype=torch.uint8, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(spec.seed)
+    for i in range(n_msgs):  # payload and AAD bytes: seeded uniform random on the device
+        a, n = lay.aad_off[i], lay.aad_lens[i]
+        if n:
+            base[a:a + n].random_(0, 256, generator=g)
+        o, n = lay.in_off[i], lay.lengths[i]
+        if n:
+            base[o:o + n].random_(0, 256, generator=g)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    slots = ctx.key_register_many(spec.keys, stream)
+    torch.cuda.synchronize()
+    key_ms = (time.perf_counter() - t0) * 1e3
+    jobs = lay.jobs([0] * n_msgs, slots, spec.ivs)
+    b = gcm.Batch(ctx, jobs, base)
+    info = b.info()
+    b.graph_launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        b.graph_launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = e0.elapsed_time(e1) / steps
+    tags_batch = base[lay.tag_base:lay.tag_base + 16 * n_msgs].clone()
+
+    # one launch sequence per message (same kernels, same results)
+    wsz = max(ctx.workspace_size(int(ln), int(al)) for ln, al in zip(spec.lengths, spec.aad_lens))
+    ws = torch.zeros(wsz, dtype=torch.uint8, device=dev)
+    views = [(base[lay.aad_off[i]:lay.aad_off[i] + lay.aad_lens[i]] if lay.aad_lens[i] else None,
+              base[lay.in_off[i]:lay.in_off[i] + lay.lengths[i]],
+              base[lay.out_off[i]:lay.out_off[i] + lay.lengths[i]],
+              base[lay.tag_base + 16 * i:lay.tag_base + 16 * i + 16]) for i in range(n_msgs)]
+
+    def per_message():
+        for i, (a, p, c, t) in enumerate(views):
+            ctx.encrypt_async(slots[i], spec.ivs[i], a, p, c, t, ws, stream)
+
+    per_message()
+    torch.cuda.synchronize()
+    same = bool(torch.equal(tags_batch, base[lay.tag_base:lay.tag_base + 16 * n_msgs]))
+    e0.record(stream)
+    per_message()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_single = e0.elapsed_time(e1)
+    b.close()
+    for s_ in slots:
+        ctx.key_release(s_)
+    payload = info["payload_bytes"]
+    del base, ws
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{n_msgs} messages, lognormal lengths (median 1 MiB, 4 KiB..64 MiB, ragged tails), "
+                    "per-message AES-128/256 key, IV and 0..4 KiB AAD, encrypt in one persistent launch "
+                    "(hipGraph replay)",
+        "payload_bytes": payload,
+        "batched_gbs": round(payload / (ms_batch * 1e-3) / 1e9, 2),
+        "batched_ms": round(ms_batch, 3),
+        "one_launch_per_message_gbs": round(payload / (ms_single * 1e-3) / 1e9, 2),
+        "one_launch_per_message_ms": round(ms_single, 3),
+        "speedup": round(ms_single / ms_batch, 3),
+        "key_setup_ms_for_all_keys": round(key_ms, 3),
+        "tags_identical_batched_vs_per_message": same,
+        "work_items": info["work_items"],
+        "wave_tiles": info["total_tiles"],
+    }
+
+
+def run_decrypt_config4(ctx, gcm, workloads, torch, n_files, side, steps):
+    """Config 4: n_files FITS-shaped ciphertexts (side x side float32 each)
+    under per-file AES-256 keys, 5% with one flipped tag or ciphertext bit;
+    decrypt-verify batch must reject exactly the tampered set."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    n_base = 8
+    bases = [workloads.fits_image_bytes(workloads.rng_for(2602, 4, 10 + k), side, side, n_sources=100)
+             for k in range(n_base)]
+    size = bases[0].size
+    hdr = [np.frombuffer(workloads.fits_header(workloads.rng_for(2602, 4, 30 + k)), np.uint8) for k in range(n_base)]
+    keys, ivs = workloads.config4_keys(n_files=n_files)
+    lay = gcm.BatchLayout([size] * n_files, [2880] * n_files)
+    base = torch.empty(lay.total, dtype=torch.uint8, device=dev)
+    dev_imgs = [torch.from_numpy(x).to(dev) for x in bases]
+    dev_hdr = [torch.from_numpy(h.copy()).to(dev) for h in hdr]
+    for i in range(n_files):
+        base[lay.in_off[i]:lay.in_off[i] + size].copy_(dev_imgs[i % n_base])
+        base[lay.aad_off[i]:lay.aad_off[i] + 2880].copy_(dev_hdr[i % n_base])
+    del dev_imgs
+    stream = torch.cuda.current_stream()
+    slots = ctx.key_register_many(keys, stream)
+    # encrypt in place to produce the ciphertexts and tags
+    enc_lay_jobs = lay.jobs([0] * n_files, slots, ivs)
+    for i in range(n_files):
+        enc_lay_jobs[i].out_off = enc_lay_jobs[i].in_off
+    gcm.Batch(ctx, enc_lay_jobs, base).launch(stream)
+    torch.cuda.synchronize()
+    plan = workloads.tamper_plan(2602, n_files)
+    for f, (where, frac, bit) in plan.items():
+        pos = lay.tag_base + 16 * f + int(frac * 16) if where == "tag" else lay.in_off[f] + int(frac * size)
+        base[pos] ^= (1 << bit)
+    jobs = lay.jobs([1] * n_files, slots, ivs)
+    b = gcm.Batch(ctx, jobs, base)
+    b.launch(stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        b.graph_launch(stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    ok = base[lay.ok_base:lay.ok_base + 4 * n_files].view(torch.int32).cpu().numpy()
+    rejected = set(int(i) for i in np.nonzero(ok == 0)[0])
+    zero_ok = all(not bool(base[lay.out_off[f]:lay.out_off[f] + size].any()) for f in list(rejected)[:8])
+    b.close()
+    for s_ in slots:
+        ctx.key_release(s_)
+    payload = size * n_files
+    del base
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"{n_files} FITS-shaped {side}x{side} float32 ciphertexts ({size} B each), per-file AES-256 "
+                    f"keys, 2880-B header AAD, {len(plan)} with one flipped tag or ciphertext bit; decrypt-verify "
+                    "in one persistent launch",
+        "payload_bytes": payload,
+        "gbs": round(payload / (ms * 1e-3) / 1e9, 2),
+        "ms": round(ms, 3),
+        "rejected_exactly_tampered_set": rejected == set(plan),
+        "n_rejected": len(rejected),
+        "rejected_outputs_zero": zero_ok,
+    }
 
 
 def main():
@@ -82,7 +235,8 @@ def main():
     tag_d = torch.zeros(16, dtype=torch.uint8, device=dev)
     ok_d = torch.zeros(1, dtype=torch.int32, device=dev)
 
-    ctx = gcm.Context(device=0, key_slots=8)
+    slots_needed = 8 + (0 if args.skip_batch else args.batch_msgs) + (0 if args.skip_dec_batch else args.dec_files)
+    ctx = gcm.Context(device=0, key_slots=slots_needed)
     if args.log2_tile or args.waves or args.gpc:
         ctx.set_launch(args.log2_tile, args.waves, args.gpc)
     ws = torch.zeros(ctx.workspace_size(n, aad_len), dtype=torch.uint8, device=dev)
@@ -167,6 +321,18 @@ def main():
                       f"{os.cpu_count()} logical CPUs visible; {dt:.1f} s",
         }
 
+    batch3 = None
+    if not args.skip_batch:
+        print("[bench] config 3 batch", file=sys.stderr, flush=True)
+        del pt_d, ct_d, back_d
+        torch.cuda.empty_cache()
+        batch3 = run_batch_config3(ctx, gcm, workloads, torch, args.batch_msgs, max(1, args.steps // 4))
+    dec4 = None
+    if not args.skip_dec_batch:
+        print("[bench] config 4 decrypt batch", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        dec4 = run_decrypt_config4(ctx, gcm, workloads, torch, args.dec_files, args.dec_side, 2)
+
     out = {
         "metric": "AES-GCM encrypt+tag GB/s vs HBM peak (1 GPU); p50/p99 latency, batched serving",
         "value": round(payload_gbs, 2),
@@ -206,6 +372,8 @@ def main():
             "algorithmic_bytes_per_launch": tile_bytes,
         },
         "cpu_baseline": cpu,
+        "batch_config3": batch3,
+        "decrypt_batch_config4": dec4,
     }
     print(json.dumps(out), flush=True)
 

@@ -183,6 +183,72 @@ int gcm_batch_destroy(gcm_batch *b);
 /* Convenience: create, launch, synchronise `stream`, destroy. */
 int gcm_batch_run(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes, void *stream);
 
+/* ---------------------------------------------------------------- serving */
+
+/* One request of the serving loop; every buffer is already in HBM. */
+typedef struct gcm_request {
+    uint32_t op;          /* 0 = encrypt, 1 = decrypt-verify */
+    uint32_t key_slot;    /* a registered (resident) key slot */
+    uint8_t iv[12];
+    uint32_t reserved;    /* must be 0 */
+    const uint8_t *aad_d; /* device, 16-byte aligned */
+    uint64_t aad_len;
+    const uint8_t *in_d;  /* device, 16-byte aligned */
+    uint8_t *out_d;       /* device, 16-byte aligned (== in_d for in place) */
+    uint64_t len;
+    uint8_t *tag_d;       /* device, 16 bytes: encrypt writes the tag, decrypt reads the expected tag */
+} gcm_request;
+
+typedef struct gcm_serve_config {
+    uint32_t n_streams;       /* batches in flight at once (0 = 4, at most 16) */
+    uint32_t max_batch_reqs;  /* requests per batch (0 = 256) */
+    uint64_t hbm_budget;      /* device bytes (in + out + AAD) of admitted requests (0 = 64 GiB) */
+    uint64_t max_batch_bytes; /* payload bytes per batch; a larger request runs alone (0 = 256 MiB) */
+    uint32_t max_queue;       /* waiting + admitted requests before submit says GCM_E_BUSY (0 = 65536) */
+    uint32_t reserved;
+} gcm_serve_config;
+
+typedef struct gcm_serve_stats {
+    uint64_t submitted, completed, rejected, batches;
+    uint64_t bytes_completed;
+    uint64_t budget_high_water;      /* most bytes ever admitted at once (<= hbm_budget) */
+    uint64_t overlapped_admissions;  /* requests admitted while another batch was on the GPU */
+    uint64_t max_inflight_batches;
+    double p50_ms, p99_ms, mean_ms, max_ms;  /* latency: submit -> result known on the host */
+    double wall_s;                           /* first submit -> last completion */
+} gcm_serve_stats;
+
+typedef struct gcm_serve gcm_serve;
+
+/* Start the serving loop (a scheduler thread and n_streams HIP streams) over
+ * the context's resident key table.  cfg may be NULL for the defaults.
+ * Continuous batching: requests are admitted in arrival order while their
+ * bytes fit the HBM budget, packed into batches (the persistent launch of
+ * gcm_batch_launch) and launched on free streams while earlier batches still
+ * run.  A request's result does not depend on what it was batched with. */
+int gcm_serve_start(gcm_ctx *ctx, const gcm_serve_config *cfg, gcm_serve **out);
+
+/* Queue a request (thread-safe, non-blocking).  GCM_E_NOMEM if it alone needs
+ * more than the budget, GCM_E_BUSY if the queue is full.  The caller keeps
+ * the buffers untouched until the request is reported done. */
+int gcm_serve_submit(gcm_serve *s, const gcm_request *req, uint64_t *id_out);
+
+/* Non-blocking status.  When *done is 1 the request is collected: *accept is
+ * the decrypt verdict (1 for encrypt) and *latency_ns its latency. */
+int gcm_serve_poll(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *latency_ns);
+
+/* Block until the request is done, then collect it as gcm_serve_poll does. */
+int gcm_serve_wait(gcm_serve *s, uint64_t id, int *accept, uint64_t *latency_ns);
+
+/* Block until every submitted request is done. */
+int gcm_serve_drain(gcm_serve *s);
+
+/* Counters and latency percentiles so far. */
+int gcm_serve_get_stats(gcm_serve *s, gcm_serve_stats *out);
+
+/* Finish queued work, stop the thread, free the serving state. */
+int gcm_serve_stop(gcm_serve *s);
+
 /* ---------------------------------------------------------------- tuning */
 
 /* Launch shape of the fused tile kernel.  Results never depend on it (the

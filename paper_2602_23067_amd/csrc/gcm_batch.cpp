@@ -104,8 +104,11 @@ extern "C" int gcm_batch_create(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, u
     for (uint32_t i = 0; i < n; ++i) {
         const gcm_job &j = jobs[i];
         const uint64_t m = (j.aad_len + 15) / 16 + (j.len + 15) / 16 + 1;
+        // about one workgroup item for small messages; items of at most
+        // waves * 2^12 blocks (1 MiB at 16 waves) for large ones, so the
+        // persistent workgroups see items of similar cost
         uint32_t log2B = std::max<uint32_t>(6, ceil_log2_u64((m + waves - 1) / waves));
-        log2B = std::min(log2B, ctx->cfg_log2B ? ctx->cfg_log2B : std::max<uint32_t>(8, log2B_cfg));
+        log2B = std::min(log2B, ctx->cfg_log2B ? ctx->cfg_log2B : std::min<uint32_t>(12, std::max<uint32_t>(8, log2B_cfg)));
         fill_desc(&descs[i], j.op, j.iv, (uint64_t)(base_d + j.aad_off), j.aad_len, (uint64_t)(base_d + j.in_off),
                   (uint64_t)(base_d + j.out_off), j.len, (uint64_t)(base_d + j.tag_off),
                   (uint64_t)(base_d + j.ok_off), (uint64_t)(ctx->d_slots + kSlotBytes * j.key_slot),

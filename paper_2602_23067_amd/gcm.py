@@ -28,6 +28,44 @@ GCM_E_SLOT = -9
 _lib: Optional[ctypes.CDLL] = None
 
 
+class Request(ctypes.Structure):
+    """Mirror of ``gcm_request``."""
+
+    _fields_ = [
+        ("op", ctypes.c_uint32),
+        ("key_slot", ctypes.c_uint32),
+        ("iv", ctypes.c_uint8 * 12),
+        ("reserved", ctypes.c_uint32),
+        ("aad_d", ctypes.c_void_p),
+        ("aad_len", ctypes.c_uint64),
+        ("in_d", ctypes.c_void_p),
+        ("out_d", ctypes.c_void_p),
+        ("len", ctypes.c_uint64),
+        ("tag_d", ctypes.c_void_p),
+    ]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [
+        ("n_streams", ctypes.c_uint32),
+        ("max_batch_reqs", ctypes.c_uint32),
+        ("hbm_budget", ctypes.c_uint64),
+        ("max_batch_bytes", ctypes.c_uint64),
+        ("max_queue", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "batches", "bytes_completed",
+                                               "budget_high_water", "overlapped_admissions",
+                                               "max_inflight_batches")] + \
+               [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s")]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class Job(ctypes.Structure):
     """Mirror of ``gcm_job`` (include/gcm_mi355.h)."""
 
@@ -81,6 +119,14 @@ def load() -> ctypes.CDLL:
         "gcm_batch_info": ([vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32)], ctypes.c_int),
         "gcm_batch_destroy": ([vp], ctypes.c_int),
         "gcm_batch_run": ([vp, vp, u32, vp, u64, vp], ctypes.c_int),
+        "gcm_serve_start": ([vp, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "gcm_serve_submit": ([vp, vp, ctypes.POINTER(u64)], ctypes.c_int),
+        "gcm_serve_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                            ctypes.POINTER(u64)], ctypes.c_int),
+        "gcm_serve_wait": ([vp, u64, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(u64)], ctypes.c_int),
+        "gcm_serve_drain": ([vp], ctypes.c_int),
+        "gcm_serve_get_stats": ([vp, vp], ctypes.c_int),
+        "gcm_serve_stop": ([vp], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "gcm_profile_read": ([vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -309,5 +355,72 @@ class Batch:
     def __del__(self):
         try:
             self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ serving
+
+class Server:
+    """Continuous-batching serving loop over a context's resident keys."""
+
+    def __init__(self, ctx: Context, n_streams: int = 4, hbm_budget: int = 64 << 30, max_batch_reqs: int = 256,
+                 max_batch_bytes: int = 256 << 20, max_queue: int = 1 << 16):
+        self._ctx = ctx
+        cfg = ServeConfig(n_streams, max_batch_reqs, hbm_budget, max_batch_bytes, max_queue, 0)
+        h = ctypes.c_void_p()
+        _check(load().gcm_serve_start(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def submit(self, op: int, slot: int, iv: bytes, aad, inp, out, tag_d) -> int:
+        r = Request()
+        r.op = op
+        r.key_slot = slot
+        r.iv[:] = list(bytes(iv))
+        r.reserved = 0
+        r.aad_d = _dev(aad) or None
+        r.aad_len = 0 if aad is None else aad.numel()
+        r.in_d = _dev(inp) or None
+        r.out_d = _dev(out) or None
+        r.len = inp.numel()
+        r.tag_d = _dev(tag_d)
+        rid = ctypes.c_uint64()
+        _check(load().gcm_serve_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._keep[rid.value] = (aad, inp, out, tag_d)
+        return rid.value
+
+    def poll(self, rid: int):
+        """None while running, else (accept, latency_ns)."""
+        done, acc, lat = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint64()
+        _check(load().gcm_serve_poll(self._h, rid, ctypes.byref(done), ctypes.byref(acc), ctypes.byref(lat)))
+        if not done.value:
+            return None
+        self._keep.pop(rid, None)
+        return bool(acc.value), lat.value
+
+    def wait(self, rid: int):
+        acc, lat = ctypes.c_int(), ctypes.c_uint64()
+        _check(load().gcm_serve_wait(self._h, rid, ctypes.byref(acc), ctypes.byref(lat)))
+        self._keep.pop(rid, None)
+        return bool(acc.value), lat.value
+
+    def drain(self) -> None:
+        _check(load().gcm_serve_drain(self._h))
+
+    def stats(self) -> dict:
+        st = ServeStats()
+        _check(load().gcm_serve_get_stats(self._h, ctypes.byref(st)))
+        return st.as_dict()
+
+    def stop(self) -> None:
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _check(load().gcm_serve_stop(h))
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.stop()
         except Exception:
             pass
