@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--batch-msgs", type=int, default=4096)
     ap.add_argument("--dec-files", type=int, default=1024)
     ap.add_argument("--dec-side", type=int, default=4096)
+    ap.add_argument("--skip-serving", action="store_true", help="skip the serving loop (config 5)")
+    ap.add_argument("--serve-docs", type=int, default=256)
+    ap.add_argument("--serve-reqs", type=int, default=3000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run three plain 1 GiB device-to-device copies first (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -208,6 +213,107 @@ def run_decrypt_config4(ctx, gcm, workloads, torch, n_files, side, steps):
     }
 
 
+def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 0.9)):
+    """Config 5: Poisson arrivals of 50/50 encrypt / decrypt-verify requests,
+    FITS-shaped lognormal sizes (median 4 MiB, 16 KiB..1 GiB, 2880 multiples)
+    with a 2880-byte header AAD, keys from a resident 1024-entry table,
+    admission by a 64 GiB HBM budget.  Request payloads come from n_docs
+    pre-generated documents (sizes drawn from the same distribution), each
+    with a fixed key and IV, pre-encrypted so decrypt requests verify; all
+    requests for one document write identical bytes to that document's
+    output buffers."""
+    import numpy as np
+
+    dev = torch.device("cuda:0")
+    seed = 2602
+    table = workloads.serving_key_table(seed)
+    stream = torch.cuda.current_stream()
+    slots = ctx.key_register_many(table, stream)
+    r = workloads.rng_for(seed, 5, 2)
+    sizes = workloads.lognormal_lengths(r, n_docs, float(4 << 20), float(np.log(2 ** 16) / 6), 16 << 10, 1 << 30)
+    sizes = (sizes + 2879) // 2880 * 2880
+    doc_key = r.integers(0, len(table), n_docs)
+    doc_iv = [workloads.random_bytes(r, 12).tobytes() for _ in range(n_docs)]
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    docs = []
+    for d in range(n_docs):
+        n = int(sizes[d])
+        pt = torch.empty(n, dtype=torch.uint8, device=dev).random_(0, 256, generator=g)
+        ct = torch.empty_like(pt)
+        aad = torch.from_numpy(np.frombuffer(workloads.fits_header(workloads.rng_for(seed, 5, 100 + d)),
+                                             np.uint8).copy()).to(dev)
+        tag = torch.zeros(16, dtype=torch.uint8, device=dev)
+        docs.append(dict(pt=pt, ct=ct, aad=aad, tag=tag, enc_out=torch.empty_like(pt), dec_out=torch.empty_like(pt),
+                         enc_tag=torch.zeros(16, dtype=torch.uint8, device=dev)))
+    wsz = max(ctx.workspace_size(int(n), 2880) for n in sizes)
+    ws = torch.zeros(wsz, dtype=torch.uint8, device=dev)
+    for d in range(n_docs):  # pre-encrypt (untimed): ciphertext + tag for the decrypt requests
+        x = docs[d]
+        ctx.encrypt_async(slots[doc_key[d]], doc_iv[d], x["aad"], x["pt"], x["ct"], x["tag"], ws, stream)
+    torch.cuda.synchronize()
+    del ws
+    mean_size = float(np.mean(sizes))
+
+    def run(n, qps, seed_off):
+        rr = workloads.rng_for(seed, 5, 3, seed_off)
+        pick = rr.integers(0, n_docs, n)
+        ops = rr.integers(0, 2, n)
+        gaps = rr.exponential(1.0 / qps, n) if qps else np.zeros(n)
+        srv = gcm.Server(ctx, n_streams=4, hbm_budget=64 << 30)
+        ids = []
+        t0 = time.perf_counter()
+        due = t0
+        for i in range(n):
+            due += gaps[i]
+            while time.perf_counter() < due:
+                pass
+            x = docs[pick[i]]
+            if ops[i] == 0:
+                ids.append(srv.submit(0, slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["pt"], x["enc_out"],
+                                      x["enc_tag"]))
+            else:
+                ids.append(srv.submit(1, slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["ct"], x["dec_out"],
+                                      x["tag"]))
+        t_sub = time.perf_counter() - t0
+        acc = [srv.wait(i)[0] for i in ids]
+        st = srv.stats()
+        srv.stop()
+        nbytes = float(sum(int(sizes[k]) for k in pick))
+        return {
+            "offered_qps": round(qps, 1) if qps else None,
+            "achieved_arrival_qps": round(n / t_sub, 1) if t_sub > 0 else None,
+            "requests": n,
+            "gbs": round(nbytes / st["wall_s"] / 1e9, 2) if st["wall_s"] else None,
+            "p50_ms": round(st["p50_ms"], 3),
+            "p99_ms": round(st["p99_ms"], 3),
+            "mean_ms": round(st["mean_ms"], 3),
+            "batches": st["batches"],
+            "max_inflight_batches": st["max_inflight_batches"],
+            "overlapped_admissions": st["overlapped_admissions"],
+            "budget_high_water_gib": round(st["budget_high_water"] / 2 ** 30, 3),
+            "all_decrypts_accepted": all(a for a, o in zip(acc, ops) if o == 1),
+        }
+
+    sat = run(n_reqs, 0.0, 0)
+    cap = sat["gbs"] * 1e9 if sat["gbs"] else 1e11
+    levels = {}
+    for k, rho in enumerate(loads):
+        levels[f"rho_{rho}"] = run(n_reqs, rho * cap / mean_size, 1 + k)
+    for s_ in slots:
+        ctx.key_release(s_)
+    del docs
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"Poisson arrivals, 50/50 encrypt / decrypt-verify, {n_docs} FITS-shaped documents with "
+                    "lognormal sizes (median 4 MiB, 16 KiB..1 GiB, 2880 multiples) and 2880-B header AAD, keys "
+                    "from a resident 1024-entry table, 64 GiB admission budget, 4 streams",
+        "mean_request_bytes": round(mean_size),
+        "saturated": sat,
+        "open_loop": levels,
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -224,6 +330,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        # a copy kernel of known size: reads 1 GiB and writes 1 GiB
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(7)
+        b_ = torch.empty_like(a)
+        for _ in range(3):
+            b_.copy_(a)
+        torch.cuda.synchronize()
+        del a, b_
     print(f"[bench] generating FITS-shaped input {args.ny}x{args.nx}", file=sys.stderr, flush=True)
     msg = workloads.config2(ny=args.ny, nx=args.nx)
     n = msg.data.size
@@ -235,7 +349,8 @@ def main():
     tag_d = torch.zeros(16, dtype=torch.uint8, device=dev)
     ok_d = torch.zeros(1, dtype=torch.int32, device=dev)
 
-    slots_needed = 8 + (0 if args.skip_batch else args.batch_msgs) + (0 if args.skip_dec_batch else args.dec_files)
+    slots_needed = 8 + max(0 if args.skip_batch else args.batch_msgs, 0 if args.skip_dec_batch else args.dec_files,
+                           0 if args.skip_serving else 1024)
     ctx = gcm.Context(device=0, key_slots=slots_needed)
     if args.log2_tile or args.waves or args.gpc:
         ctx.set_launch(args.log2_tile, args.waves, args.gpc)
@@ -333,6 +448,12 @@ def main():
         torch.cuda.empty_cache()
         dec4 = run_decrypt_config4(ctx, gcm, workloads, torch, args.dec_files, args.dec_side, 2)
 
+    serve5 = None
+    if not args.skip_serving:
+        print("[bench] config 5 serving", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        serve5 = run_serving_config5(ctx, gcm, workloads, torch, args.serve_docs, args.serve_reqs)
+
     out = {
         "metric": "AES-GCM encrypt+tag GB/s vs HBM peak (1 GPU); p50/p99 latency, batched serving",
         "value": round(payload_gbs, 2),
@@ -374,6 +495,7 @@ def main():
         "cpu_baseline": cpu,
         "batch_config3": batch3,
         "decrypt_batch_config4": dec4,
+        "serving_config5": serve5,
     }
     print(json.dumps(out), flush=True)
 

@@ -258,6 +258,29 @@ int gcm_serve_stop(gcm_serve *s);
  * workgroups per compute unit (0 = automatic). */
 int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group, uint32_t groups_per_cu);
 
+/* Result of one autotune point. */
+typedef struct gcm_tune_result {
+    uint32_t log2_tile_blocks; /* chosen blocks per wave tile (log2) */
+    uint32_t waves_per_group;  /* chosen workgroup size in waves */
+    uint32_t candidates;       /* shapes timed */
+    float best_ms;             /* mean time of the chosen shape (one encrypt pass) */
+    double gbs;                /* payload GB/s of the chosen shape */
+} gcm_tune_result;
+
+/* Exhaustive launch-shape search for messages of about `len` bytes under
+ * `key_len`-byte keys (the paper's per-GPU parameter sweep): every candidate
+ * tile size (blocks per lane) and workgroup size is timed `reps` times with
+ * HIP events on a scratch message, all candidates must produce the identical
+ * tag, and the fastest shape is cached for that (key size, size bucket) and
+ * used by every later call without an explicit gcm_set_launch.  Allocates
+ * scratch for the duration of the call; blocks until done. */
+int gcm_autotune(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32_t reps, gcm_tune_result *out, void *stream);
+
+/* Persist / restore the autotune cache as JSON (restoring rejects a cache
+ * written on another GPU architecture). */
+int gcm_autotune_save(gcm_ctx *ctx, const char *path);
+int gcm_autotune_load(gcm_ctx *ctx, const char *path);
+
 /* ---------------------------------------------------------------- measurement */
 
 /* Kernel timing for benchmarks.  While enabled, every launch of the fused

@@ -101,6 +101,8 @@ extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_byt
 
     int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), 2 * 256 * sizeof(uint32_t));
     if (rc == GCM_OK)
+        rc = ctx_alloc(ctx, &ctx->d_frob, frob_table_bytes());
+    if (rc == GCM_OK)
         rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_slots), kSlotBytes * key_slots);
     if (rc == GCM_OK)
         rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_io), 256);
@@ -110,7 +112,7 @@ extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_byt
             rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
     }
     if (rc == GCM_OK) {
-        e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, nullptr);
+        e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, ctx->d_frob, nullptr);
         if (e == hipSuccess)
             e = hipDeviceSynchronize();
         if (e != hipSuccess)
@@ -134,6 +136,7 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     ctx_free(ctx, ctx->d_tables, 2 * 256 * sizeof(uint32_t));
+    ctx_free(ctx, ctx->d_frob, frob_table_bytes());
     ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
     ctx_free(ctx, ctx->d_io, 256);
     ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
@@ -186,7 +189,7 @@ int gcm::register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const ui
         addrs[i] = (uint64_t)(ctx->d_slots + kSlotBytes * picked[i]);
     hipError_t e = hipSetDevice(ctx->device);
     if (e == hipSuccess)
-        e = launch_key_setup(keys, key_lens, addrs.data(), n, ctx->d_tables, ctx->d_tables + 256, s);
+        e = launch_key_setup(keys, key_lens, addrs.data(), n, ctx->d_tables, ctx->d_tables + 256, ctx->d_frob, s);
     if (e != hipSuccess)
         return fail_hip(e, "key setup launch");
     for (uint32_t i = 0; i < n; ++i) {
@@ -291,6 +294,19 @@ void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t
     *log2B = std::min<uint32_t>(16, std::max<uint32_t>(8, l));
 }
 
+void gcm::message_shape(const gcm_ctx *ctx, uint32_t nr, uint64_t len, uint64_t aad_len, uint32_t *log2B,
+                        uint32_t *waves, uint32_t *gpc)
+{
+    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+    launch_shape(ctx, m, log2B, waves, gpc);
+    uint32_t tl, tw;
+    if (!ctx->cfg_log2B && !ctx->cfg_waves && tuned_shape(ctx, (nr - 6) * 4, len, &tl, &tw)) {
+        *log2B = tl;
+        *waves = tw;
+        *gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)tw);
+    }
+}
+
 void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in,
                     uint64_t out, uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr,
                     uint32_t log2B, uint32_t waves, uint64_t tile_base)
@@ -318,6 +334,7 @@ void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, ui
     d->log2B = log2B;
     d->nr = nr;
     d->groups = (uint32_t)((d->n_tiles + waves - 1) / waves);
+    d->fix_lane = 1;  // callers that mix many keys switch large-table fix-ups off per message
 }
 
 int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
@@ -371,10 +388,15 @@ extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_
 {
     if (!ctx)
         return 0;
-    uint32_t log2B, waves, gpc;
+    std::lock_guard<std::mutex> g(ctx->mu);
     const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    launch_shape(ctx, m, &log2B, &waves, &gpc);
-    const uint64_t T = (m + (1ull << log2B) - 1) >> log2B;
+    uint32_t best = 64;
+    for (uint32_t nr : {10u, 12u, 14u}) {  // any key size the call may use
+        uint32_t log2B, waves, gpc;
+        message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
+        best = std::min(best, log2B);
+    }
+    const uint64_t T = (m + (1ull << best) - 1) >> best;
     return workspace_bytes_for(T, 1);
 }
 
@@ -467,7 +489,7 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
         return fail_hip(e, "hipSetDevice");
     uint32_t log2B, waves, gpc;
     const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    launch_shape(ctx, m, &log2B, &waves, &gpc);
+    message_shape(ctx, slot_nr(key_len), len, aad_len, &log2B, &waves, &gpc);
     const uint64_t T = (m + (1ull << log2B) - 1) >> log2B;
     rc = ensure_ws_locked(ctx, workspace_bytes_for(T, 1));
     if (rc)

@@ -16,6 +16,7 @@ struct gcm_ctx {
     uint64_t budget = 0;  // 0 = unbounded
     uint64_t used = 0;
     uint32_t *d_tables = nullptr;  // TE0[256] then S-box[256] (as words)
+    void *d_frob = nullptr;        // Frobenius tables x -> x^(2^k), k = 1..47
     uint8_t *d_slots = nullptr;    // n_slots * kSlotBytes
     uint32_t n_slots = 0;
     std::vector<uint8_t> slot_used;
@@ -31,6 +32,8 @@ struct gcm_ctx {
     uint8_t *h_io = nullptr;  // pinned mirror
     // launch shape overrides (0 = automatic)
     uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0;
+    // autotune cache: (key bytes << 32 | floor(log2 len)) -> (log2 tile blocks, waves)
+    std::unordered_map<uint64_t, std::pair<uint32_t, uint32_t>> tuned;
     // tile-kernel timing (events recorded on the launch stream)
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
@@ -42,6 +45,9 @@ namespace gcm {
 
 constexpr uint64_t kMaxLen = (1ull << 36) - 32;  // 2^39 - 256 bits
 constexpr uint64_t kMaxAad = (1ull << 61) - 1;   // < 2^64 bits
+// batch/serving messages at least this long use the per-lane fix-up tables
+// (512 KiB per key, shared by the message's many work items)
+constexpr uint64_t kLaneFixMinBytes = 64ull << 20;
 
 int fail(int code, const char *fmt, ...);
 int fail_hip(hipError_t e, const char *what);
@@ -53,6 +59,10 @@ int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_
                          uint32_t *slots_out, hipStream_t s);
 
 void launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc);
+// shape for one message: explicit settings, else the autotune cache, else the heuristic
+void message_shape(const gcm_ctx *ctx, uint32_t nr, uint64_t len, uint64_t aad_len, uint32_t *log2B, uint32_t *waves,
+                   uint32_t *gpc);
+bool tuned_shape(const gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32_t *log2B, uint32_t *waves);
 void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in, uint64_t out,
                uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr, uint32_t log2B,
                uint32_t waves, uint64_t tile_base);
@@ -64,9 +74,10 @@ hipError_t prof_begin(gcm_ctx *ctx, hipStream_t s);
 hipError_t prof_end(gcm_ctx *ctx, hipStream_t s);
 
 // kernels (gcm_kernels.hip)
-hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s);
+hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, void *frob, hipStream_t s);
+size_t frob_table_bytes();
 hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens, const uint64_t *slot_addrs,
-                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, hipStream_t s);
+                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, const void *frob, hipStream_t s);
 hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, uint32_t n_items,
                         const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
                         hipStream_t s);

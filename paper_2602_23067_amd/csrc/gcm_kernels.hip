@@ -116,12 +116,15 @@ __global__ void k_init_tables(uint32_t *te0, uint32_t *sbox)
     }
 }
 
-// Plain one-block AES from global tables (key setup and E_K(J0) only).
-__device__ void aes_block_global(const uint32_t *rk, int nr, const uint32_t *te0, const uint32_t *sb,
-                                 const uint32_t in[4], uint32_t out[4])
+// One AES block with a fully unrolled round count (key setup and E_K(J0)
+// only); te0/sb point at LDS copies, rk at registers or LDS.
+template <int NR>
+__device__ __forceinline__ void aes_block(const uint32_t *rk, const uint32_t *te0, const uint32_t *sb,
+                                          const uint32_t in[4], uint32_t out[4])
 {
     uint32_t s0 = in[0] ^ rk[0], s1 = in[1] ^ rk[1], s2 = in[2] ^ rk[2], s3 = in[3] ^ rk[3];
-    for (int r = 1; r < nr; ++r) {
+#pragma unroll
+    for (int r = 1; r < NR; ++r) {
         const uint32_t t0 = te0[s0 & 0xff] ^ rotl32(te0[(s1 >> 8) & 0xff], 8) ^ rotl32(te0[(s2 >> 16) & 0xff], 16) ^
                             rotl32(te0[s3 >> 24], 24) ^ rk[4 * r + 0];
         const uint32_t t1 = te0[s1 & 0xff] ^ rotl32(te0[(s2 >> 8) & 0xff], 8) ^ rotl32(te0[(s3 >> 16) & 0xff], 16) ^
@@ -136,13 +139,24 @@ __device__ void aes_block_global(const uint32_t *rk, int nr, const uint32_t *te0
         s3 = t3;
     }
     out[0] = (sb[s0 & 0xff] | (sb[(s1 >> 8) & 0xff] << 8) | (sb[(s2 >> 16) & 0xff] << 16) | (sb[s3 >> 24] << 24)) ^
-             rk[4 * nr + 0];
+             rk[4 * NR + 0];
     out[1] = (sb[s1 & 0xff] | (sb[(s2 >> 8) & 0xff] << 8) | (sb[(s3 >> 16) & 0xff] << 16) | (sb[s0 >> 24] << 24)) ^
-             rk[4 * nr + 1];
+             rk[4 * NR + 1];
     out[2] = (sb[s2 & 0xff] | (sb[(s3 >> 8) & 0xff] << 8) | (sb[(s0 >> 16) & 0xff] << 16) | (sb[s1 >> 24] << 24)) ^
-             rk[4 * nr + 2];
+             rk[4 * NR + 2];
     out[3] = (sb[s3 & 0xff] | (sb[(s0 >> 8) & 0xff] << 8) | (sb[(s1 >> 16) & 0xff] << 16) | (sb[s2 >> 24] << 24)) ^
-             rk[4 * nr + 3];
+             rk[4 * NR + 3];
+}
+
+__device__ __forceinline__ void aes_block_nr(int nr, const uint32_t *rk, const uint32_t *te0, const uint32_t *sb,
+                                             const uint32_t in[4], uint32_t out[4])
+{
+    if (nr == 10)
+        aes_block<10>(rk, te0, sb, in, out);
+    else if (nr == 12)
+        aes_block<12>(rk, te0, sb, in, out);
+    else
+        aes_block<14>(rk, te0, sb, in, out);
 }
 
 // ---------------------------------------------------------------- key setup
@@ -192,15 +206,6 @@ __device__ __forceinline__ u32x4 poly_to_mem(P128 p)
                  brev_bytes((uint32_t)(p.hi >> 32))};
 }
 
-// multiply by x modulo x^128 + x^7 + x^2 + x + 1
-__device__ __forceinline__ P128 poly_mulx(P128 v)
-{
-    const uint64_t carry = v.hi >> 63;
-    v.hi = (v.hi << 1) | (v.lo >> 63);
-    v.lo = (v.lo << 1) ^ (carry ? 0x87ull : 0ull);
-    return v;
-}
-
 // spread the 32 bits of x to the even bit positions of a 64-bit word
 __device__ __forceinline__ uint64_t spread32(uint32_t x)
 {
@@ -230,95 +235,243 @@ __device__ P128 poly_square(P128 a)
     return r;
 }
 
+// fold (l0, l1) + (h0, h1) * x^128 back below x^128 (x^128 = x^7 + x^2 + x + 1)
+__device__ __forceinline__ P128 poly_reduce(uint64_t l0, uint64_t l1, uint64_t h0, uint64_t h1)
+{
+    uint64_t tlo = h0 ^ (h0 << 1) ^ (h0 << 2) ^ (h0 << 7);
+    uint64_t thi = h1 ^ ((h1 << 1) | (h0 >> 63)) ^ ((h1 << 2) | (h0 >> 62)) ^ ((h1 << 7) | (h0 >> 57));
+    const uint64_t ov = (h1 >> 63) ^ (h1 >> 62) ^ (h1 >> 57);
+    tlo ^= ov ^ (ov << 1) ^ (ov << 2) ^ (ov << 7);
+    P128 r;
+    r.lo = l0 ^ tlo;
+    r.hi = l1 ^ thi;
+    return r;
+}
+
+// v * x^i for 0 <= i < 128: a 256-bit shift, then one fold
+__device__ __forceinline__ P128 poly_mul_xi(P128 v, int i)
+{
+    uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+    if (i == 0) {
+        w0 = v.lo;
+        w1 = v.hi;
+    } else if (i < 64) {
+        w0 = v.lo << i;
+        w1 = (v.hi << i) | (v.lo >> (64 - i));
+        w2 = v.hi >> (64 - i);
+    } else if (i == 64) {
+        w1 = v.lo;
+        w2 = v.hi;
+    } else {
+        const int j = i - 64;
+        w1 = v.lo << j;
+        w2 = (v.hi << j) | (v.lo >> (64 - j));
+        w3 = v.hi >> (64 - j);
+    }
+    return poly_reduce(w0, w1, w2, w3);
+}
+
+// Frobenius tables: squaring is GF(2)-linear and does not depend on the key,
+// so x -> x^(2^k) has a fixed byte-position table F_k (16 x 256 entries).
+// Built once per context; key setup then forms all H^(2^k) in parallel, one
+// lane per k, instead of a chain of 47 squarings.
+__global__ __launch_bounds__(256) void k_frob_tables(u32x4 *frob)
+{
+    __shared__ u32x4 basis[128];  // (x^i)^(2^k), memory order
+    const int k = blockIdx.x + 1;
+    const int tid = threadIdx.x;
+    if (tid < 128) {
+        P128 v;
+        v.lo = tid < 64 ? (1ull << tid) : 0ull;
+        v.hi = tid < 64 ? 0ull : (1ull << (tid - 64));
+        for (int q = 0; q < k; ++q)
+            v = poly_square(v);
+        basis[tid] = poly_to_mem(v);
+    }
+    __syncthreads();
+    u32x4 *tab = frob + (uint64_t)blockIdx.x * 4096;
+    for (int e = tid; e < 4096; e += 256) {
+        const int j = e >> 8, b = e & 255;
+        u32x4 acc = {0, 0, 0, 0};
+        for (int t = 0; t < 8; ++t)
+            if ((b >> t) & 1)
+                acc ^= basis[8 * j + 7 - t];
+        tab[e] = acc;
+    }
+}
+
+// FIPS-197 key expansion with the key length fixed at compile time (fully
+// unrolled, so the schedule stays in registers), then H = E_K(0^128).
+template <int NK>
+__device__ __forceinline__ void expand_and_hash(const KeyArg &key, KeySlotHdr *hd, const uint32_t *te0,
+                                                const uint32_t *sb, uint32_t h[4])
+{
+    constexpr int NR = NK + 6, NW = 4 * (NR + 1);
+    uint32_t w[NW];
+#pragma unroll
+    for (int i = 0; i < NK; ++i)
+        w[i] = key.w[i];
+    uint32_t rcon = 1;
+#pragma unroll
+    for (int i = NK; i < NW; ++i) {
+        uint32_t t = w[i - 1];
+        if (i % NK == 0) {
+            t = sub_word((t >> 8) | (t << 24), sb) ^ rcon;
+            rcon = gf8_xtime(rcon);
+        } else if (NK > 6 && i % NK == 4) {
+            t = sub_word(t, sb);
+        }
+        w[i] = w[i - NK] ^ t;
+    }
+#pragma unroll
+    for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
+        hd->rk[i] = i < NW ? w[i] : 0u;
+    hd->nr = (uint32_t)NR;
+    hd->key_len = (uint32_t)(4 * NK);
+    const uint32_t zero[4] = {0, 0, 0, 0};
+    aes_block<NR>(w, te0, sb, zero, h);
+}
+
 // One workgroup per key (blockIdx.x indexes `keys`/`slots`): the AES tables
 // are staged in LDS, then one thread derives the round keys, H = E_K(0^128)
 // and H^(2^k) by repeated squaring.
-__global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t *te0g, const uint32_t *sbg)
+__global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t *te0g, const uint32_t *sbg,
+                                                  const u32x4 *__restrict__ frob)
 {
     __shared__ uint32_t te0[256], sb[256];
+    __shared__ uint32_t h_sh[4];
     for (int i = threadIdx.x; i < 256; i += 64) {
         te0[i] = te0g[i];
         sb[i] = sbg[i];
     }
     __syncthreads();
-    if (threadIdx.x != 0)
-        return;
     const KeyArg key = chunk.keys[blockIdx.x];
     KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(chunk.slots[blockIdx.x]);
-    const int nk = (int)key.len / 4, nr = nk + 6;
-    uint32_t w[4 * (kMaxNr + 1)];
-    for (int i = 0; i < nk; ++i)
-        w[i] = key.w[i];
-    uint32_t rcon = 1;
-    for (int i = nk; i < 4 * (nr + 1); ++i) {
-        uint32_t t = w[i - 1];
-        if (i % nk == 0) {
-            t = sub_word((t >> 8) | (t << 24), sb) ^ rcon;
-            rcon = gf8_xtime(rcon);
-        } else if (nk > 6 && i % nk == 4) {
-            t = sub_word(t, sb);
+    if (threadIdx.x == 0) {
+        uint32_t h[4];
+        if (key.len == 16)
+            expand_and_hash<4>(key, hd, te0, sb, h);
+        else if (key.len == 24)
+            expand_and_hash<6>(key, hd, te0, sb, h);
+        else
+            expand_and_hash<8>(key, hd, te0, sb, h);
+        for (int i = 0; i < 4; ++i) {
+            hd->h[i] = h[i];
+            h_sh[i] = h[i];
         }
-        w[i] = w[i - nk] ^ t;
     }
-    for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
-        hd->rk[i] = i < 4 * (nr + 1) ? w[i] : 0u;
-    hd->nr = (uint32_t)nr;
-    hd->key_len = key.len;
-    const uint32_t zero[4] = {0, 0, 0, 0};
-    uint32_t h[4];
-    aes_block_global(w, nr, te0, sb, zero, h);
-    for (int i = 0; i < 4; ++i)
-        hd->h[i] = h[i];
-    P128 p = mem_to_poly(h);
-    for (int k = 0; k < kPowLevels; ++k) {
-        const u32x4 m = poly_to_mem(p);
-        hd->hpow[k][0] = m.x;
-        hd->hpow[k][1] = m.y;
-        hd->hpow[k][2] = m.z;
-        hd->hpow[k][3] = m.w;
-        p = poly_square(p);
+    __syncthreads();
+    // H^(2^k) = F_k(H): lane k applies its Frobenius table (F_0 is the identity)
+    const int k = threadIdx.x;
+    if (k < kPowLevels) {
+        const u32x4 H = u32x4{h_sh[0], h_sh[1], h_sh[2], h_sh[3]};
+        u32x4 r = H;
+        if (k > 0) {
+            const u32x4 *F = frob + (uint64_t)(k - 1) * 4096;
+            r = u32x4{0, 0, 0, 0};
+            for (int j = 0; j < 16; ++j)
+                r ^= F[j * 256 + byte_of(H, j)];
+        }
+        hd->hpow[k][0] = r.x;
+        hd->hpow[k][1] = r.y;
+        hd->hpow[k][2] = r.z;
+        hd->hpow[k][3] = r.w;
     }
 }
 
 // Fixed-multiplier tables.  Block b < kTab4Levels builds the nibble-position
 // table of H^(2^b); the last block builds the byte-position table of
 // H^(2^kStrideLevel) = H^64, the per-lane Horner multiplier of the tile kernel.
+// a * b for one operand pair, all 64 lanes of the wave cooperating: lane i
+// contributes the terms of bits i and i+64 of a (b * x^i, b * x^(i+64)), then
+// an XOR across the wave sums them.  Every lane returns the product.
+__device__ u32x4 gf_mul_wave(u32x4 a, u32x4 b)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t am[4] = {a.x, a.y, a.z, a.w};
+    const P128 pa = mem_to_poly(am);
+    const uint32_t bm[4] = {b.x, b.y, b.z, b.w};
+    const P128 pb = mem_to_poly(bm);
+    P128 acc;
+    acc.lo = 0;
+    acc.hi = 0;
+    if ((pa.lo >> lane) & 1) {
+        const P128 t = poly_mul_xi(pb, lane);
+        acc.lo ^= t.lo;
+        acc.hi ^= t.hi;
+    }
+    if ((pa.hi >> lane) & 1) {
+        const P128 t = poly_mul_xi(pb, lane + 64);
+        acc.lo ^= t.lo;
+        acc.hi ^= t.hi;
+    }
+    u32x4 r = poly_to_mem(acc);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        r.x ^= __shfl_xor(r.x, off, 64);
+        r.y ^= __shfl_xor(r.y, off, 64);
+        r.z ^= __shfl_xor(r.z, off, 64);
+        r.w ^= __shfl_xor(r.w, off, 64);
+    }
+    return r;
+}
+
+// Fixed-multiplier tables of one key (grid.y indexes the key).
+//   blocks 0..39:   nibble-position table of H^(2^b)      (fix-ups, combine tree)
+//   block 40:       byte-position table of H^64           (per-lane Horner multiplier)
+//   blocks 41..104: nibble-position table of H^e, e = 0..63 (per-lane tile fix-up)
 __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
 {
     __shared__ u32x4 basis[128];  // basis[i] = M * x^i, memory order
+    __shared__ u32x4 m_sh;
     uint8_t *slot = reinterpret_cast<uint8_t *>(chunk.slots[blockIdx.y]);
     const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
     const int b = blockIdx.x;
-    const int lvl = b < kTab4Levels ? b : kStrideLevel;
     const int tid = threadIdx.x;
-    if (tid < 128) {
-        P128 v = mem_to_poly(hd->hpow[lvl]);
-        for (int s = 0; s < tid; ++s)
-            v = poly_mulx(v);
-        basis[tid] = poly_to_mem(v);
+    if (b <= kTab4Levels) {
+        if (tid == 0) {
+            const int lvl = b < kTab4Levels ? b : kStrideLevel;
+            m_sh = u32x4{hd->hpow[lvl][0], hd->hpow[lvl][1], hd->hpow[lvl][2], hd->hpow[lvl][3]};
+        }
+    } else if (tid < 64) {
+        // H^e as the product of H^(2^k) over the set bits of e (one wave)
+        const int e = b - kTab4Levels - 1;
+        u32x4 m = {0x80u, 0u, 0u, 0u};  // the field's one
+        for (int k = 0; k < 6; ++k)
+            if ((e >> k) & 1)
+                m = gf_mul_wave(m, u32x4{hd->hpow[k][0], hd->hpow[k][1], hd->hpow[k][2], hd->hpow[k][3]});
+        if (tid == 0)
+            m_sh = m;
     }
     __syncthreads();
-    if (b < kTab4Levels) {
-        u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes);
-        for (int e = tid; e < 512; e += 256) {
-            const int j = e >> 4, nib = e & 15;
-            const int byte = j >> 1, shift = (j & 1) ? 0 : 4;  // even j: high nibble
-            u32x4 acc = {0, 0, 0, 0};
-            for (int t = 0; t < 4; ++t)
-                if ((nib >> t) & 1)
-                    acc ^= basis[8 * byte + 7 - (t + shift)];
-            tab[e] = acc;
-        }
-    } else {
+    if (tid < 128) {
+        const uint32_t mm[4] = {m_sh.x, m_sh.y, m_sh.z, m_sh.w};
+        basis[tid] = poly_to_mem(poly_mul_xi(mem_to_poly(mm), tid));
+    }
+    __syncthreads();
+    if (b == kTab4Levels) {
         u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab8Off);
         for (int e = tid; e < 4096; e += 256) {
             const int k = e >> 8, v = e & 255;
             u32x4 acc = {0, 0, 0, 0};
-            for (int s = 0; s < 8; ++s)
-                if ((v >> s) & 1)
-                    acc ^= basis[8 * k + 7 - s];
+            for (int t = 0; t < 8; ++t)
+                if ((v >> t) & 1)
+                    acc ^= basis[8 * k + 7 - t];
             tab[e] = acc;
         }
+        return;
+    }
+    u32x4 *tab = b < kTab4Levels
+                     ? reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes)
+                     : reinterpret_cast<u32x4 *>(slot + kSlotLaneOff + (uint64_t)(b - kTab4Levels - 1) * kTab4Bytes);
+    for (int e = tid; e < 512; e += 256) {
+        const int j = e >> 4, nib = e & 15;
+        const int byte = j >> 1, shift = (j & 1) ? 0 : 4;  // even j: high nibble
+        u32x4 acc = {0, 0, 0, 0};
+        for (int t = 0; t < 4; ++t)
+            if ((nib >> t) & 1)
+                acc ^= basis[8 * byte + 7 - (t + shift)];
+        tab[e] = acc;
     }
 }
 
@@ -340,6 +493,27 @@ __device__ __forceinline__ u32x4 mul_tab4(u32x4 a, const u32x4 *__restrict__ tab
         }
     }
     return r0 ^ r1;
+}
+
+// a * M from a nibble table in global memory, gathers issued sixteen at a time
+__device__ __forceinline__ u32x4 mul_tab4_wide(u32x4 a, const u32x4 *__restrict__ tab)
+{
+    u32x4 r = {0, 0, 0, 0};
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        u32x4 g[16];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int k = 8 * half + q;
+            const uint32_t byte = byte_of(a, k);
+            g[2 * q] = tab[(2 * k) * 16 + (byte >> 4)];
+            g[2 * q + 1] = tab[(2 * k + 1) * 16 + (byte & 15)];
+        }
+#pragma unroll
+        for (int q = 0; q < 16; q += 2)
+            r = xor3v(r, g[q], g[q + 1]);
+    }
+    return r;
 }
 
 // a * H^e for 0 <= e < 2^bits using the tables of H^(2^(level0 + k))
@@ -586,7 +760,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         if (v0 >= na && v0 + 64 <= na + nfull) {
             // all 64 lanes hold whole data blocks
             const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
-            const u32x4 x = __builtin_nontemporal_load(in_g + j);
+            const u32x4 x = in_g[j];
             const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
             const u32x4 o = x ^ ks;
             __builtin_nontemporal_store(o, out_g + j);
@@ -613,8 +787,21 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         }
     }
 
-    // fix-up: a * H^(63 - lane), exponent bits through the H^(2^k) tables
-    a = mul_hpow(a, (uint64_t)(63 - lane), 6, reinterpret_cast<const uint8_t *>(d.slot), 0);
+    // fix-up: a * H^(63 - lane).  Messages whose key tables are shared by many
+    // tiles use one multiply with that lane's table; others walk the exponent
+    // bits through the six H^(2^k) tables (48 KiB instead of 512 KiB per key).
+    if (d.fix_lane) {
+        a = mul_tab4_wide(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLaneOff) + (uint64_t)(63 - lane) * 512);
+    } else {
+        const uint32_t e = 63u - (uint32_t)lane;
+        const u32x4 *lv = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab4Off);
+#pragma unroll 1
+        for (int k = 0; k < 6; ++k) {
+            const u32x4 m = mul_tab4_wide(a, lv + (uint64_t)k * 512);
+            if ((e >> k) & 1)
+                a = m;
+        }
+    }
     a = wave_xor_reduce(a);
     if (lane == 0)
         partials[d.tile_base + t] = a;
@@ -693,7 +880,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
 {
     __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
     __shared__ u32x4 red[kCombineThreads / 64];
-    __shared__ uint32_t s_te0[256], s_sb[256];
+    __shared__ uint32_t s_te0[256], s_sb[256], s_rk[4 * (kMaxNr + 1)];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
     const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
@@ -718,15 +905,30 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
             s_te0[i] = te0g[i];
             s_sb[i] = sbg[i];
         }
+        if (i < 4 * (kMaxNr + 1))
+            s_rk[i] = reinterpret_cast<const KeySlotHdr *>(slot)->rk[i];
     }
     __syncthreads();
 
     u32x4 acc = {0, 0, 0, 0};
     if (i < T) {
         uint64_t t_last = i;
-        for (uint64_t t = i; t < T; t += kCombineThreads) {
-            acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ partials[d.tile_base + t];
-            t_last = t;
+        // partials are loaded eight at a time ahead of the dependent Horner steps
+        for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
+            u32x4 pv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+                pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+                if (t < T) {
+                    acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ pv[q];
+                    t_last = t;
+                }
+            }
         }
         const uint64_t e = T - 1 - t_last;
         for (int k = 0; k < nbits; ++k) {
@@ -747,7 +949,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
         const uint32_t j0[4] = {d.iv[0], d.iv[1], d.iv[2], 0x01000000u};
         uint32_t ek[4];
-        aes_block_global(hd->rk, (int)hd->nr, s_te0, s_sb, j0, ek);
+        aes_block_nr((int)hd->nr, s_rk, s_te0, s_sb, j0, ek);
         const u32x4 tag = s ^ u32x4{ek[0], ek[1], ek[2], ek[3]};
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         if (d.op == 0) {
@@ -790,16 +992,22 @@ __global__ __launch_bounds__(256) void k_gcm_zerofill(const MsgDesc *__restrict_
 
 // ---------------------------------------------------------------- host-side launchers
 
-hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, hipStream_t s)
+hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, void *frob, hipStream_t s)
 {
     hipLaunchKernelGGL(k_init_tables, dim3(1), dim3(256), 0, s, te0, sbox);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_frob_tables, dim3(kPowLevels - 1), dim3(256), 0, s, reinterpret_cast<u32x4 *>(frob));
     return hipGetLastError();
 }
+
+size_t frob_table_bytes() { return (size_t)(kPowLevels - 1) * 4096 * 16; }
 
 // Expand n keys (key i: key_lens[i] bytes at keys + key_off[i]) into the
 // slots at slot_addrs[i], in launches of kKeyChunk keys.
 hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens, const uint64_t *slot_addrs,
-                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, hipStream_t s)
+                            uint32_t n, const uint32_t *te0, const uint32_t *sbox, const void *frob, hipStream_t s)
 {
     for (uint32_t base = 0; base < n; base += kKeyChunk) {
         const uint32_t m = n - base < (uint32_t)kKeyChunk ? n - base : (uint32_t)kKeyChunk;
@@ -815,11 +1023,11 @@ hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens
             kc.slots[j] = slot_addrs[base + j];
             sc.slots[j] = slot_addrs[base + j];
         }
-        hipLaunchKernelGGL(k_key_setup, dim3(m), dim3(64), 0, s, kc, te0, sbox);
+        hipLaunchKernelGGL(k_key_setup, dim3(m), dim3(64), 0, s, kc, te0, sbox, reinterpret_cast<const u32x4 *>(frob));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1, m), dim3(256), 0, s, sc);
+        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLaneTabs, m), dim3(256), 0, s, sc);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

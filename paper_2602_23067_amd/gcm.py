@@ -66,6 +66,11 @@ class ServeStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [("log2_tile_blocks", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32),
+                ("candidates", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("gbs", ctypes.c_double)]
+
+
 class Job(ctypes.Structure):
     """Mirror of ``gcm_job`` (include/gcm_mi355.h)."""
 
@@ -127,6 +132,9 @@ def load() -> ctypes.CDLL:
         "gcm_serve_drain": ([vp], ctypes.c_int),
         "gcm_serve_get_stats": ([vp, vp], ctypes.c_int),
         "gcm_serve_stop": ([vp], ctypes.c_int),
+        "gcm_autotune": ([vp, u32, u64, u32, vp, vp], ctypes.c_int),
+        "gcm_autotune_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "gcm_autotune_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "gcm_profile_read": ([vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     }
@@ -267,6 +275,18 @@ class Context:
         return n.value, ms.value
 
     # -------------------------------------------------------- tuning
+    def autotune(self, key_len: int, length: int, reps: int = 3, stream=None) -> dict:
+        r = TuneResult()
+        _check(load().gcm_autotune(self._h, key_len, length, reps, ctypes.byref(r), _stream(stream)))
+        return {"log2_tile_blocks": r.log2_tile_blocks, "waves_per_group": r.waves_per_group,
+                "candidates": r.candidates, "best_ms": r.best_ms, "gbs": r.gbs}
+
+    def autotune_save(self, path: str) -> None:
+        _check(load().gcm_autotune_save(self._h, path.encode()))
+
+    def autotune_load(self, path: str) -> None:
+        _check(load().gcm_autotune_load(self._h, path.encode()))
+
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
         _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))
 

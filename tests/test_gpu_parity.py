@@ -208,3 +208,28 @@ def test_argument_errors(ctx):
     with pytest.raises(gcm.GcmError) as e:
         ctx.key_release(63)
     assert e.value.code == gcm.GCM_E_SLOT
+
+
+def test_autotune_picks_a_shape_and_results_stay_exact(ctx, tmp_path):
+    """Every candidate shape must give the identical tag (checked inside the
+    search); afterwards the cached shape is used and results still match the
+    oracle; the cache survives a save/load round trip."""
+    res = ctx.autotune(32, 3 << 20, reps=2)
+    print("autotune:", res, flush=True)
+    assert res["candidates"] >= 2 and res["waves_per_group"] in (8, 16) and 8 <= res["log2_tile_blocks"] <= 14
+    r = workloads.rng_for(37)
+    key, iv = workloads.random_bytes(r, 32).tobytes(), workloads.random_bytes(r, 12).tobytes()
+    _check_case(ctx, key, iv, workloads.random_bytes(r, 50), workloads.random_bytes(r, (3 << 20) + 5))
+    path = str(tmp_path / "tune.json")
+    ctx.autotune_save(path)
+    c2 = gcm.Context(device=0, key_slots=4)
+    try:
+        c2.autotune_load(path)
+        key2 = workloads.random_bytes(r, 32).tobytes()
+        pt = workloads.random_bytes(r, 3 << 20)
+        rct, rtag = oracle.gcm_encrypt(key2, iv, b"", pt)
+        pt_d = to_dev(pt)
+        ct_d = torch.empty_like(pt_d)
+        assert c2.encrypt(key2, iv, None, pt_d, ct_d) == rtag and np.array_equal(host(ct_d), rct)
+    finally:
+        c2.close()
