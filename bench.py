@@ -35,7 +35,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ny", type=int, default=16384)
     ap.add_argument("--nx", type=int, default=16384)
-    ap.add_argument("--cpu-sample-mib", type=int, default=24)
+    ap.add_argument("--cpu-sample-mib", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--latency-iters", type=int, default=200)
     ap.add_argument("--log2-tile", type=int, default=0)
@@ -52,6 +52,26 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three plain 1 GiB device-to-device copies first (HBM counter calibration)")
     return ap.parse_args()
+
+
+def measured_traffic(algorithmic_bytes):
+    """HBM bytes per launch of the tile kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, if it was taken on this exact kernel
+    source (else None: the counters would describe another kernel)."""
+    import hashlib
+
+    prof = os.path.join(ROOT, "profiles", "k_gcm_tiles_fits1gib_aes256_traffic.json")
+    src = os.path.join(ROOT, "paper_2602_23067_amd", "csrc", "gcm_kernels.hip")
+    try:
+        with open(prof) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != digest:
+        return None
+    return int(rec["traffic_bytes_per_launch"])
 
 
 def cpu_model() -> str:
@@ -488,7 +508,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(tile_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(tile_bytes) if (args.ny, args.nx) == (16384, 16384) else None,
             "tile_kernel_ms": round(tile_ms, 4),
             "algorithmic_bytes_per_launch": tile_bytes,
         },
