@@ -451,13 +451,14 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
     __syncthreads();
     if (b == kTab4Levels) {
         u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab8Off);
+        // entry-major: (byte value v at position k) * M at index 16*v + k
         for (int e = tid; e < 4096; e += 256) {
             const int k = e >> 8, v = e & 255;
             u32x4 acc = {0, 0, 0, 0};
             for (int t = 0; t < 8; ++t)
                 if ((v >> t) & 1)
                     acc ^= basis[8 * k + 7 - t];
-            tab[e] = acc;
+            tab[16 * v + k] = acc;
         }
         return;
     }
@@ -543,16 +544,21 @@ __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 // ---------------------------------------------------------------- fused tile kernel
 //
 // LDS layout (128 KiB, one workgroup per CU):
-//   [0, 64 KiB)        byte-position GHASH table of H^64 for the current key
-//                      (16 positions x 256 entries x 16 B): lookup k of a
-//                      block reads entry (k, byte k) with one b128 read whose
-//                      immediate offset is k*4096.
+//   [0, 64 KiB)        byte-position GHASH table of H^64 for the current key,
+//                      entry-major: the product for byte value v at position
+//                      k sits at byte 256*v + 16*k, so position k lives in
+//                      bank group k (16 groups of four banks).
 //   [64 KiB, 128 KiB)  AES T-tables: entry e of table t, copy c (c = 0..15)
 //                      at 0x10000 + 256*e + 64*t + 4*c.
 //
-// gfx950 LDS has 32 four-byte banks and resolves a wave64 access over all 64
-// lanes, so random indices into one 1 KiB table cost about three times the
-// conflict-free two cycles.  Here the bank of a T-table read depends only on
+// A wave64 ds_read_b32 takes two cycles when no two lanes of a half-wave
+// share a bank; random indices into one 1 KiB table cost about three times
+// that.  A ds_read_b128 serves 16 lanes per cycle, four banks each, so its
+// 16 lanes must fall in 16 different bank groups.  The GHASH lookups get that
+// from the schedule: in lookup j lane l reads position (j + l) & 15, with its
+// accumulator held byte-rotated by l & 15 so that position is byte j of the
+// rotated value; 16 consecutive lanes then read 16 different positions.
+//  Here the bank of a T-table read depends only on
 // (t, c): lane l uses copy c = l & 15, and lane group g = (l >> 4) & 3 keeps
 // its AES state rotated left by 8g bits.  Because T_t = rotl(T_0, 8t), a
 // rotated state turns "table r, byte r" into "table (r+g)&3, byte (r+g)&3",
@@ -653,19 +659,62 @@ __device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const CO
     return u32x4{rotr_by(o0, lk.unrot), rotr_by(o1, lk.unrot), rotr_by(o2, lk.unrot), rotr_by(o3, lk.unrot)};
 }
 
-// a * H^64 with the byte-position table in LDS (16 lookups of 16 bytes)
-__device__ __forceinline__ u32x4 ghash_mul8(u32x4 a, const u32x4 *__restrict__ tab)
+// Per-lane constants of the GHASH lookup schedule (q = lane & 15):
+// pos[m] byte t = 16 * ((4m + t + q) & 15), the bank-group offset of lookup
+// j = 4m + t; the accumulator is rotated by q bytes as a dword rotation by
+// q >> 2 (two conditional swaps) and a byte shift of 8 * (q & 3) bits.
+struct GhK {
+    uint32_t pos[4];
+    uint32_t sh;
+    bool s2, s1;
+};
+
+__device__ __forceinline__ GhK gh_constants(int lane)
 {
+    GhK g;
+    const uint32_t q = (uint32_t)lane & 15u;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        uint32_t w = 0;
+        for (int t = 0; t < 4; ++t)
+            w |= (((4u * m + t + q) & 15u) << 4) << (8 * t);
+        g.pos[m] = w;
+    }
+    g.sh = 8u * (q & 3u);
+    g.s2 = (q & 8u) != 0;
+    g.s1 = (q & 4u) != 0;
+    return g;
+}
+
+// byte i of the result is byte (i + q) & 15 of a
+__device__ __forceinline__ u32x4 rot_bytes_lane(u32x4 a, const GhK &g)
+{
+    const u32x4 c = g.s2 ? u32x4{a.z, a.w, a.x, a.y} : a;
+    const u32x4 b = g.s1 ? u32x4{c.y, c.z, c.w, c.x} : c;
+    return u32x4{__builtin_amdgcn_alignbit(b.y, b.x, g.sh), __builtin_amdgcn_alignbit(b.z, b.y, g.sh),
+                 __builtin_amdgcn_alignbit(b.w, b.z, g.sh), __builtin_amdgcn_alignbit(b.x, b.w, g.sh)};
+}
+
+// a * H^64 + x with the entry-major byte-position table at LDS offset 0
+// (16 lookups of 16 bytes, conflict-free across each 16-lane group)
+__device__ __forceinline__ u32x4 ghash_mul8(u32x4 a, u32x4 x, const uint8_t *__restrict__ lds, const GhK &g)
+{
+    const u32x4 r = rot_bytes_lane(a, g);
+    const uint32_t w[4] = {r.x, r.y, r.z, r.w};
     u32x4 e[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k)
-        e[k] = tab[k * 256 + byte_of(a, k)];
+    for (int j = 0; j < 16; ++j) {
+        // address = 256 * (byte j of r) + 16 * position
+        const uint32_t sel = 0x0c0c0000u | ((4u + (uint32_t)(j & 3)) << 8) | (uint32_t)(j & 3);
+        const uint32_t addr = __builtin_amdgcn_perm(w[j >> 2], g.pos[j >> 2], sel);
+        e[j] = *reinterpret_cast<const u32x4 *>(lds + addr);
+    }
     const u32x4 p0 = xor3v(e[0], e[1], e[2]);
     const u32x4 p1 = xor3v(e[3], e[4], e[5]);
     const u32x4 p2 = xor3v(e[6], e[7], e[8]);
     const u32x4 p3 = xor3v(e[9], e[10], e[11]);
     const u32x4 p4 = xor3v(e[12], e[13], e[14]);
-    return xor3v(xor3v(p0, p1, p2), xor3v(p3, p4, e[15]), u32x4{0, 0, 0, 0});
+    return xor3v(xor3v(p0, p1, p2), xor3v(p3, p4, e[15]), x);
 }
 
 // zero-padded load of block `blk` of a buffer of `total` bytes
@@ -721,12 +770,11 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // across the wave.
 template <int NR>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
-                          u32x4 *__restrict__ partials)
+                          const GhK &gk, u32x4 *__restrict__ partials)
 {
     const int lane = threadIdx.x & 63;
     const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
     const CONST_AS uint32_t *rk = rk_base;
-    const u32x4 *tab8 = reinterpret_cast<const u32x4 *>(lds);
     AesCtx c;
     {
         const uint32_t s0 = d.iv[0] ^ rk[0], s1 = d.iv[1] ^ rk[1], s2 = d.iv[2] ^ rk[2];
@@ -764,7 +812,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
             const u32x4 o = x ^ ks;
             __builtin_nontemporal_store(o, out_g + j);
-            a = ghash_mul8(a, tab8) ^ (enc ? o : x);
+            a = ghash_mul8(a, enc ? o : x, lds, gk);
         } else {
             // boundary row: zero padding, AAD, partial blocks or the length block
             const int64_t v = v0 + lane;
@@ -783,7 +831,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
                 X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
                           bswap32((uint32_t)cbits)};
             }
-            a = ghash_mul8(a, tab8) ^ X;
+            a = ghash_mul8(a, X, lds, gk);
         }
     }
 
@@ -826,6 +874,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             w[i] = rotl32(te0g[i >> 6], 8 * ((i >> 4) & 3));
     }
     const LaneK lk = lane_constants(threadIdx.x & 63);
+    const GhK gk = gh_constants(threadIdx.x & 63);
 
     uint64_t cur_slot = 0;
     const int wave = threadIdx.x >> 6;
@@ -851,11 +900,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.n_tiles) {
             if (d.nr == 10)
-                wave_tile<10>(d, t, lds, lk, partials);
+                wave_tile<10>(d, t, lds, lk, gk, partials);
             else if (d.nr == 12)
-                wave_tile<12>(d, t, lds, lk, partials);
+                wave_tile<12>(d, t, lds, lk, gk, partials);
             else
-                wave_tile<14>(d, t, lds, lk, partials);
+                wave_tile<14>(d, t, lds, lk, gk, partials);
         }
     }
 }
