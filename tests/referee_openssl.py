@@ -10,6 +10,8 @@ import ctypes
 import ctypes.util
 from typing import Optional
 
+import numpy as np
+
 _EVP_CTRL_GCM_SET_IVLEN = 0x9
 _EVP_CTRL_GCM_GET_TAG = 0x10
 _EVP_CTRL_GCM_SET_TAG = 0x11
@@ -113,5 +115,32 @@ def gcm_decrypt(key: bytes, iv: bytes, aad: bytes, ct: bytes, tag: bytes):
         assert L.EVP_CIPHER_CTX_ctrl(ctx, _EVP_CTRL_GCM_SET_TAG, 16, tbuf) == 1
         ok = L.EVP_DecryptFinal_ex(ctx, None, ctypes.byref(n)) == 1
         return out.raw[: len(ct)], ok
+    finally:
+        L.EVP_CIPHER_CTX_free(ctx)
+
+
+def gcm_encrypt_np(key: bytes, iv: bytes, aad: bytes, pt: np.ndarray):
+    """AES-GCM of a large contiguous uint8 array without Python-level copies:
+    returns (ciphertext array, 16-byte tag)."""
+    L = _load()
+    pt = np.ascontiguousarray(pt, dtype=np.uint8).reshape(-1)
+    out = np.empty_like(pt)
+    ctx = L.EVP_CIPHER_CTX_new()
+    try:
+        assert L.EVP_EncryptInit_ex(ctx, _cipher("gcm", len(key)), None, None, None) == 1
+        assert L.EVP_CIPHER_CTX_ctrl(ctx, _EVP_CTRL_GCM_SET_IVLEN, len(iv), None) == 1
+        assert L.EVP_EncryptInit_ex(ctx, None, None, key, iv) == 1
+        n = ctypes.c_int(0)
+        if aad:
+            assert L.EVP_EncryptUpdate(ctx, None, ctypes.byref(n), aad, len(aad)) == 1
+        step = 1 << 28
+        for off in range(0, pt.size, step):
+            m = min(step, pt.size - off)
+            assert L.EVP_EncryptUpdate(ctx, ctypes.c_void_p(out.ctypes.data + off), ctypes.byref(n),
+                                       ctypes.c_void_p(pt.ctypes.data + off), m) == 1
+        assert L.EVP_EncryptFinal_ex(ctx, None, ctypes.byref(n)) == 1
+        tag = ctypes.create_string_buffer(16)
+        assert L.EVP_CIPHER_CTX_ctrl(ctx, _EVP_CTRL_GCM_GET_TAG, 16, tag) == 1
+        return out, tag.raw
     finally:
         L.EVP_CIPHER_CTX_free(ctx)
