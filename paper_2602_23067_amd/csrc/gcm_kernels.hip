@@ -623,21 +623,14 @@ struct AesCtx {
     uint32_t rk3;             // round key 0, column 3
 };
 
-// Keystream block for counter value `ctr` (big-endian in bytes 12..15).
-// Only column 3 of the counter block varies, so round 1 needs four table
-// lookups instead of sixteen (counter-mode caching).
-template <int NR>
-__device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const CONST_AS uint32_t *rk,
-                                         const uint8_t *lds, const LaneK &lk)
+// Rounds R0..NR of AES on a lane-rotated state (rounds R0..NR-1 with the
+// T-tables, the last with S-box bytes only).
+template <int R0, int NR>
+__device__ __forceinline__ u32x4 aes_rounds(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
+                                            const CONST_AS uint32_t *rk, const uint8_t *lds, const LaneK &lk)
 {
-    const uint32_t v = bswap32(ctr) ^ c.rk3;
-    const uint32_t w3 = rotr_by(v, lk.rot);  // rotl(v, 8g)
-    uint32_t s0 = rotr_by(c.u0, lk.rot) ^ LK(3, w3);
-    uint32_t s1 = rotr_by(c.u1, lk.rot) ^ LK(2, w3);
-    uint32_t s2 = rotr_by(c.u2, lk.rot) ^ LK(1, w3);
-    uint32_t s3 = rotr_by(c.u3, lk.rot) ^ LK(0, w3);
 #pragma unroll
-    for (int r = 2; r < NR; ++r) {
+    for (int r = R0; r < NR; ++r) {
         const uint32_t k0 = rotr_by(rk[4 * r + 0], lk.rot), k1 = rotr_by(rk[4 * r + 1], lk.rot);
         const uint32_t k2 = rotr_by(rk[4 * r + 2], lk.rot), k3 = rotr_by(rk[4 * r + 3], lk.rot);
         const uint32_t t0 = xor3(xor3(LK(0, s0), LK(1, s1), LK(2, s2)), LK(3, s3), k0);
@@ -657,6 +650,68 @@ __device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const CO
     const uint32_t o2 = bsel(lk.mask[0], LL(0, s2), bsel(lk.mask[1], LL(1, s3), bsel(lk.mask[2], LL(2, s0), LL(3, s1)))) ^ k2;
     const uint32_t o3 = bsel(lk.mask[0], LL(0, s3), bsel(lk.mask[1], LL(1, s0), bsel(lk.mask[2], LL(2, s1), LL(3, s2)))) ^ k3;
     return u32x4{rotr_by(o0, lk.unrot), rotr_by(o1, lk.unrot), rotr_by(o2, lk.unrot), rotr_by(o3, lk.unrot)};
+}
+
+// Keystream block for counter value `ctr` (big-endian in bytes 12..15).
+// Only column 3 of the counter block varies, so round 1 needs four table
+// lookups instead of sixteen (counter-mode caching).
+template <int NR>
+__device__ __forceinline__ u32x4 aes_ctr(uint32_t ctr, const AesCtx &c, const CONST_AS uint32_t *rk,
+                                         const uint8_t *lds, const LaneK &lk)
+{
+    const uint32_t v = bswap32(ctr) ^ c.rk3;
+    const uint32_t w3 = rotr_by(v, lk.rot);  // rotl(v, 8g)
+    const uint32_t s0 = rotr_by(c.u0, lk.rot) ^ LK(3, w3);
+    const uint32_t s1 = rotr_by(c.u1, lk.rot) ^ LK(2, w3);
+    const uint32_t s2 = rotr_by(c.u2, lk.rot) ^ LK(1, w3);
+    const uint32_t s3 = rotr_by(c.u3, lk.rot) ^ LK(0, w3);
+    return aes_rounds<2, NR>(s0, s1, s2, s3, rk, lds, lk);
+}
+
+// Counter-mode caching through round 2.  With counter bytes 12..14 fixed,
+// round 1 leaves state columns 1..3 fixed and only column 0 depends on the
+// low counter byte; every round-2 output column then takes exactly one
+// table entry indexed by a byte of that column, XOR a word that depends only
+// on the upper 24 counter bits.  Ctr2 holds those four words (unrotated).
+struct Ctr2 {
+    uint32_t v0, v1, v2, v3;
+};
+
+// T_t[x] = rotl(T0[x], 8t) read through the scalar cache (uniform x)
+__device__ __forceinline__ uint32_t te_s(const CONST_AS uint32_t *te, int t, uint32_t x)
+{
+    return rotl32(te[x], 8 * t);
+}
+
+// the four round-2 words for upper counter bits `hi` (wave-uniform)
+__device__ __forceinline__ Ctr2 ctr_round2(uint32_t hi, const AesCtx &c, const CONST_AS uint32_t *rk,
+                                           const CONST_AS uint32_t *te)
+{
+    const uint32_t v = bswap32(hi << 8) ^ c.rk3;  // column 3 of the first state (byte 3 unused)
+    const uint32_t u1 = c.u1 ^ te_s(te, 2, B2(v));
+    const uint32_t u2 = c.u2 ^ te_s(te, 1, B1(v));
+    const uint32_t u3 = c.u3 ^ te_s(te, 0, B0(v));
+    Ctr2 q;
+    q.v0 = te_s(te, 1, B1(u1)) ^ te_s(te, 2, B2(u2)) ^ te_s(te, 3, B3(u3)) ^ rk[8];
+    q.v1 = te_s(te, 0, B0(u1)) ^ te_s(te, 1, B1(u2)) ^ te_s(te, 2, B2(u3)) ^ rk[9];
+    q.v2 = te_s(te, 0, B0(u2)) ^ te_s(te, 1, B1(u3)) ^ te_s(te, 3, B3(u1)) ^ rk[10];
+    q.v3 = te_s(te, 0, B0(u3)) ^ te_s(te, 2, B2(u1)) ^ te_s(te, 3, B3(u2)) ^ rk[11];
+    return q;
+}
+
+// Keystream block for `ctr` whose upper 24 bits match `q`: one lookup in
+// round 1 and four in round 2 instead of four and sixteen.
+template <int NR>
+__device__ __forceinline__ u32x4 aes_ctr2(uint32_t ctr, const Ctr2 &q, const AesCtx &c,
+                                          const CONST_AS uint32_t *rk, const uint8_t *lds, const LaneK &lk)
+{
+    const uint32_t w3 = rotr_by((ctr << 24) ^ c.rk3, lk.rot);  // byte 3: low counter byte ^ key
+    const uint32_t x0 = rotr_by(c.u0, lk.rot) ^ LK(3, w3);      // round-1 column 0
+    const uint32_t s0 = rotr_by(q.v0, lk.rot) ^ LK(0, x0);
+    const uint32_t s1 = rotr_by(q.v1, lk.rot) ^ LK(3, x0);
+    const uint32_t s2 = rotr_by(q.v2, lk.rot) ^ LK(2, x0);
+    const uint32_t s3 = rotr_by(q.v3, lk.rot) ^ LK(1, x0);
+    return aes_rounds<3, NR>(s0, s1, s2, s3, rk, lds, lk);
 }
 
 // Per-lane constants of the GHASH lookup schedule (q = lane & 15):
@@ -770,9 +825,10 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // across the wave.
 template <int NR>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
-                          const GhK &gk, u32x4 *__restrict__ partials)
+                          const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
 {
     const int lane = threadIdx.x & 63;
+    const CONST_AS uint32_t *te = cptr<uint32_t>(te0g);
     const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
     const CONST_AS uint32_t *rk = rk_base;
     AesCtx c;
@@ -799,6 +855,8 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     GLOBAL_AS u32x4 *out_g = gptr<u32x4>(d.out);
 
     u32x4 a = {0, 0, 0, 0};
+    uint32_t hc = 0xffffffffu;  // upper counter bits `cur` belongs to (none yet)
+    Ctr2 cur = {0, 0, 0, 0};
     for (uint32_t r = r0; r < R; ++r) {
         // re-read the round keys with scalar loads each row instead of holding
         // 4*(Nr+1) of them (or their lane-rotated copies) in registers
@@ -809,7 +867,24 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             // all 64 lanes hold whole data blocks
             const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
             const u32x4 x = in_g[j];
-            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
+            // counters of this row: base + lane (mod 2^32); the upper 24 bits
+            // change at most once inside a row, and then by one
+            const uint32_t base = (uint32_t)(v0 - na) + 2u;
+            const uint32_t h = base >> 8;
+            if (h != hc) {
+                cur = ctr_round2(h, c, rk, te);
+                hc = h;
+            }
+            Ctr2 q = cur;
+            if ((base & 255u) > 192u) {
+                const uint32_t h1 = (h + 1u) & 0xffffffu;
+                const Ctr2 nxt = ctr_round2(h1, c, rk, te);
+                const bool up = (base & 255u) + (uint32_t)lane > 255u;
+                q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
+                cur = nxt;
+                hc = h1;
+            }
+            const u32x4 ks = aes_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
             const u32x4 o = x ^ ks;
             __builtin_nontemporal_store(o, out_g + j);
             a = ghash_mul8(a, enc ? o : x, lds, gk);
@@ -877,7 +952,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
     const GhK gk = gh_constants(threadIdx.x & 63);
 
     uint64_t cur_slot = 0;
-    const int wave = threadIdx.x >> 6;
+    const int wave = (int)uniform(threadIdx.x >> 6);  // wave-uniform: row bookkeeping stays scalar
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         MsgDesc d;
         uint32_t first;
@@ -900,11 +975,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.n_tiles) {
             if (d.nr == 10)
-                wave_tile<10>(d, t, lds, lk, gk, partials);
+                wave_tile<10>(d, t, lds, lk, gk, te0g, partials);
             else if (d.nr == 12)
-                wave_tile<12>(d, t, lds, lk, gk, partials);
+                wave_tile<12>(d, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile<14>(d, t, lds, lk, gk, partials);
+                wave_tile<14>(d, t, lds, lk, gk, te0g, partials);
         }
     }
 }
