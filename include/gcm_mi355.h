@@ -117,7 +117,8 @@ int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const u
 
 /* Device scratch bytes an asynchronous call on a message of `len` data bytes
  * and `aad_len` AAD bytes needs (the per-tile partial hashes of the map
- * phase).  A workspace may be reused by calls that are ordered on one stream. */
+ * phase and the block E_K(J0) that the reduce phase adds).  A workspace may be
+ * reused by calls that are ordered on one stream. */
 uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
 
 /* Same computation as gcm_encrypt, fully on the device and without host

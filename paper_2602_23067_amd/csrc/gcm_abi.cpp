@@ -352,17 +352,20 @@ int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const 
     return GCM_OK;
 }
 
+uint64_t gcm::workspace_counter_bytes(uint64_t n_msgs) { return ((4 + 4 * n_msgs) + 255) / 256 * 256; }
+
+// counters, then per message its tile partials followed by one 16-byte slot
+// for E_K(J0)
 uint64_t gcm::workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs)
 {
-    const uint64_t counters = ((4 + 4 * n_msgs) + 255) / 256 * 256;
-    return counters + 16 * total_tiles;
+    return workspace_counter_bytes(n_msgs) + 16 * (total_tiles + n_msgs);
 }
 
 // Enqueue the kernels for one message on `s`.
 int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
 {
     uint32_t *counters = reinterpret_cast<uint32_t *>(ws);
-    uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_bytes_for(0, 1);
+    uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1);
     const uint32_t items = d.groups;
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(items, (uint32_t)ctx->cu_count * gpc));
     hipError_t e = prof_begin(ctx, s);
@@ -371,7 +374,7 @@ int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t 
     if (e == hipSuccess)
         e = prof_end(ctx, s);
     if (e == hipSuccess)
-        e = launch_combine(nullptr, 1, &d, ctx->d_tables, ctx->d_tables + 256, partials, counters, s);
+        e = launch_combine(nullptr, 1, &d, partials, counters, s);
     if (e == hipSuccess && d.op == 1) {
         const uint64_t chunks = (d.len / 16 + 255) / 256;
         const uint32_t zgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 4096));

@@ -115,11 +115,11 @@ extern "C" int gcm_batch_create(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, u
                   ctx->slot_nr[j.key_slot], log2B, waves, tile_base);
         // per-lane fix-up tables only pay off when many work items share the key
         descs[i].fix_lane = j.len >= kLaneFixMinBytes ? 1u : 0u;
-        tile_base += descs[i].n_tiles;
+        tile_base += descs[i].n_tiles + 1;  // partials, then the E_K(J0) slot
+        b->total_tiles += descs[i].n_tiles;
         b->any_decrypt |= j.op == 1;
         b->payload_bytes += j.len;
     }
-    b->total_tiles = tile_base;
 
     // work items, messages grouped by key slot
     std::vector<uint32_t> order(n);
@@ -166,7 +166,7 @@ static hipError_t batch_enqueue(gcm_batch *b, hipStream_t s)
     if (b->n == 0)
         return hipSuccess;
     uint32_t *counters = reinterpret_cast<uint32_t *>(b->d_ws);
-    uint8_t *partials = b->d_ws + workspace_bytes_for(0, b->n);
+    uint8_t *partials = b->d_ws + workspace_counter_bytes(b->n);
     hipError_t e = prof_begin(ctx, s);
     if (e == hipSuccess)
         e = launch_tiles((int)b->waves, b->d_descs, b->d_items, b->n_items, nullptr, ctx->d_tables, partials, counters,
@@ -174,7 +174,7 @@ static hipError_t batch_enqueue(gcm_batch *b, hipStream_t s)
     if (e == hipSuccess)
         e = prof_end(ctx, s);
     if (e == hipSuccess)
-        e = launch_combine(b->d_descs, b->n, nullptr, ctx->d_tables, ctx->d_tables + 256, partials, counters, s);
+        e = launch_combine(b->d_descs, b->n, nullptr, partials, counters, s);
     if (e == hipSuccess && b->any_decrypt)
         e = launch_zerofill(b->d_descs, nullptr, counters, (uint32_t)std::max(1, ctx->cu_count * 4), s);
     return e;

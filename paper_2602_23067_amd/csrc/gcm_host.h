@@ -67,6 +67,7 @@ void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_
                uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr, uint32_t log2B,
                uint32_t waves, uint64_t tile_base);
 int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
+uint64_t workspace_counter_bytes(uint64_t n_msgs);
 uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
 int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
 // bracket the next tile launch with events when profiling is on (caller holds ctx->mu)
@@ -82,8 +83,8 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
                         const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
                         hipStream_t s);
 int max_groups_per_cu(int waves);
-hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const uint32_t *te0,
-                          const uint32_t *sbox, const void *partials, uint32_t *counters, hipStream_t s);
+hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
+                          uint32_t *counters, hipStream_t s);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);
 

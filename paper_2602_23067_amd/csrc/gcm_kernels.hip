@@ -116,8 +116,7 @@ __global__ void k_init_tables(uint32_t *te0, uint32_t *sbox)
     }
 }
 
-// One AES block with a fully unrolled round count (key setup and E_K(J0)
-// only); te0/sb point at LDS copies, rk at registers or LDS.
+// One AES block with a fully unrolled round count (key setup only); te0/sb point at LDS copies, rk at registers or LDS.
 template <int NR>
 __device__ __forceinline__ void aes_block(const uint32_t *rk, const uint32_t *te0, const uint32_t *sb,
                                           const uint32_t in[4], uint32_t out[4])
@@ -146,17 +145,6 @@ __device__ __forceinline__ void aes_block(const uint32_t *rk, const uint32_t *te
              rk[4 * NR + 2];
     out[3] = (sb[s3 & 0xff] | (sb[(s0 >> 8) & 0xff] << 8) | (sb[(s1 >> 16) & 0xff] << 16) | (sb[s2 >> 24] << 24)) ^
              rk[4 * NR + 3];
-}
-
-__device__ __forceinline__ void aes_block_nr(int nr, const uint32_t *rk, const uint32_t *te0, const uint32_t *sb,
-                                             const uint32_t in[4], uint32_t out[4])
-{
-    if (nr == 10)
-        aes_block<10>(rk, te0, sb, in, out);
-    else if (nr == 12)
-        aes_block<12>(rk, te0, sb, in, out);
-    else
-        aes_block<14>(rk, te0, sb, in, out);
 }
 
 // ---------------------------------------------------------------- key setup
@@ -841,6 +829,14 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         c.rk3 = rk[3];
     }
 
+    if (t == 0) {
+        // E_K(J0) is the keystream block of counter value 1; the wave that owns
+        // tile 0 leaves it after the message's partials for the combine
+        const u32x4 ek = aes_ctr<NR>(1u, c, rk, lds, lk);
+        if (lane == 0)
+            partials[d.tile_base + d.n_tiles] = ek;
+    }
+
     const uint64_t B = 1ull << d.log2B;
     const uint32_t R = (uint32_t)(B >> 6);
     const int64_t vbase = (int64_t)(t * B) - (int64_t)d.z;  // GHASH index of lane 0, row 0
@@ -994,21 +990,27 @@ constexpr int kCombineLog2 = 10;
 // lifts its value by H^((T-1-t_last)*B) through the exponent bits, and the
 // XOR over threads closes the tree; one more *H accounts for GHASH's final
 // multiplication.  The nibble tables this needs (at most 12 of 8 KiB) are
-// staged in LDS first, so every multiply is 32 LDS reads.
+// staged in LDS first, so every multiply is 32 LDS reads.  E_K(J0) was left
+// by the tile kernel right after the message's T partials.
 template <bool BATCH>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
-                                                                 const uint32_t *__restrict__ te0g,
-                                                                 const uint32_t *__restrict__ sbg,
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
 {
     __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
     __shared__ u32x4 red[kCombineThreads / 64];
-    __shared__ uint32_t s_te0[256], s_sb[256], s_rk[4 * (kMaxNr + 1)];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
     const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
+
+    // the first eight partials of this thread, loaded ahead of the table staging
+    u32x4 pv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const uint64_t t = (uint64_t)i + (uint64_t)q * kCombineThreads;
+        pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+    }
 
     // exponent bits needed for T-1-t_last < min(T, 1024), and whether any
     // thread owns more than one partial
@@ -1025,25 +1027,19 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
             const int lvl = tix == 0 ? 0 : (int)d.log2B + tix - 1;
             tabs[tix][e & 511] = g[(uint64_t)lvl * 512 + (e & 511)];
         }
-        if (i < 256) {
-            s_te0[i] = te0g[i];
-            s_sb[i] = sbg[i];
-        }
-        if (i < 4 * (kMaxNr + 1))
-            s_rk[i] = reinterpret_cast<const KeySlotHdr *>(slot)->rk[i];
     }
     __syncthreads();
 
     u32x4 acc = {0, 0, 0, 0};
     if (i < T) {
         uint64_t t_last = i;
-        // partials are loaded eight at a time ahead of the dependent Horner steps
         for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
-            u32x4 pv[8];
+            if (t0 != i) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
-                pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+                for (int q = 0; q < 8; ++q) {
+                    const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+                    pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+                }
             }
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
@@ -1070,11 +1066,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         for (int w = 1; w < kCombineThreads / 64; ++w)
             s ^= red[w];
         s = mul_tab4(s, tabs[0]);  // * H
-        const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
-        const uint32_t j0[4] = {d.iv[0], d.iv[1], d.iv[2], 0x01000000u};
-        uint32_t ek[4];
-        aes_block_nr((int)hd->nr, s_rk, s_te0, s_sb, j0, ek);
-        const u32x4 tag = s ^ u32x4{ek[0], ek[1], ek[2], ek[3]};
+        const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         if (d.op == 0) {
             uint8_t *dst = reinterpret_cast<uint8_t *>(d.tag);
@@ -1203,15 +1195,15 @@ int max_groups_per_cu(int waves)
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
-hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const uint32_t *te0,
-                          const uint32_t *sbox, const void *partials, uint32_t *counters, hipStream_t s)
+hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
+                          uint32_t *counters, hipStream_t s)
 {
     const u32x4 *p = reinterpret_cast<const u32x4 *>(partials);
     if (descs)
-        hipLaunchKernelGGL(k_gcm_combine<true>, dim3(n_msgs), dim3(kCombineThreads), 0, s, descs, MsgDesc{}, te0, sbox,
-                           p, counters);
+        hipLaunchKernelGGL(k_gcm_combine<true>, dim3(n_msgs), dim3(kCombineThreads), 0, s, descs, MsgDesc{}, p,
+                           counters);
     else
-        hipLaunchKernelGGL(k_gcm_combine<false>, dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, te0, sbox, p,
+        hipLaunchKernelGGL(k_gcm_combine<false>, dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, p,
                            counters);
     return hipGetLastError();
 }

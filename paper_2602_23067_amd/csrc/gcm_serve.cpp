@@ -121,7 +121,7 @@ static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &ba
     launch_shape(ctx, std::max<uint64_t>(1, total_m), &log2B_cfg, &waves, &gpc);
 
     std::vector<MsgDesc> descs(n);
-    uint64_t tile_base = 0, n_items = 0;
+    uint64_t tile_base = 0, n_tiles = 0, n_items = 0;
     bool any_dec = false;
     for (uint32_t i = 0; i < n; ++i) {
         const gcm_request &r = s->reqs[batch[i].id].r;
@@ -134,12 +134,13 @@ static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &ba
                   (uint64_t)r.tag_d, 0, (uint64_t)(ctx->d_slots + kSlotBytes * r.key_slot), ctx->slot_nr[r.key_slot],
                   l, waves, tile_base);
         descs[i].fix_lane = r.len >= kLaneFixMinBytes ? 1u : 0u;
-        tile_base += descs[i].n_tiles;
+        tile_base += descs[i].n_tiles + 1;  // partials, then the E_K(J0) slot
+        n_tiles += descs[i].n_tiles;
         n_items += descs[i].groups;
         any_dec |= r.op == 1;
     }
     const uint64_t desc_b = align256(n * sizeof(MsgDesc)), item_b = align256(n_items * sizeof(WorkItem));
-    const uint64_t flag_b = align256(4ull * n), ws_b = workspace_bytes_for(tile_base, n);
+    const uint64_t flag_b = align256(4ull * n), ws_b = workspace_bytes_for(n_tiles, n);
     int rc = slot_reserve(s, sl, desc_b + item_b + flag_b + ws_b, desc_b + item_b + flag_b);
     if (rc)
         return rc;
@@ -162,12 +163,12 @@ static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &ba
     const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_items, (uint64_t)ctx->cu_count * gpc));
     hipError_t e = hipMemcpyAsync(sl.d_mem, sl.h_mem, desc_b + item_b, hipMemcpyHostToDevice, sl.stream);
     uint32_t *counters = reinterpret_cast<uint32_t *>(d_ws);
-    uint8_t *partials = d_ws + workspace_bytes_for(0, n);
+    uint8_t *partials = d_ws + workspace_counter_bytes(n);
     if (e == hipSuccess)
         e = launch_tiles((int)waves, d_desc, d_item, (uint32_t)n_items, nullptr, ctx->d_tables, partials, counters, grid,
                          sl.stream);
     if (e == hipSuccess)
-        e = launch_combine(d_desc, n, nullptr, ctx->d_tables, ctx->d_tables + 256, partials, counters, sl.stream);
+        e = launch_combine(d_desc, n, nullptr, partials, counters, sl.stream);
     if (e == hipSuccess && any_dec)
         e = launch_zerofill(d_desc, nullptr, counters, (uint32_t)std::max(1, ctx->cu_count * 2), sl.stream);
     if (e == hipSuccess && any_dec)
