@@ -255,7 +255,7 @@ int gcm_serve_stop(gcm_serve *s);
 /* Launch shape of the fused tile kernel.  Results never depend on it (the
  * counter and GHASH exponents derive from block indices only); only speed
  * does.  log2_tile_blocks: blocks per wave tile (6..20, 0 = automatic);
- * waves_per_group: 8 or 16 (0 = automatic); groups_per_cu: resident
+ * waves_per_group: 8, 12 or 16 (0 = automatic); groups_per_cu: resident
  * workgroups per compute unit (0 = automatic). */
 int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group, uint32_t groups_per_cu);
 

@@ -161,8 +161,8 @@ extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t 
         return fail(GCM_E_ARG, "gcm_set_launch: NULL context");
     if (log2_tile_blocks && (log2_tile_blocks < 6 || log2_tile_blocks > 20))
         return fail(GCM_E_ARG, "gcm_set_launch: log2_tile_blocks must be 0 or 6..20");
-    if (waves_per_group && waves_per_group != 8 && waves_per_group != 16)
-        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 8 or 16");
+    if (waves_per_group && waves_per_group != 8 && waves_per_group != 12 && waves_per_group != 16)
+        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 8, 12 or 16");
     if (groups_per_cu > 64)
         return fail(GCM_E_ARG, "gcm_set_launch: groups_per_cu must be <= 64");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -288,10 +288,28 @@ void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t
         *log2B = ctx->cfg_log2B;
         return;
     }
-    // about two wave tiles per resident wave, at least 4 rows per tile
-    const uint64_t resident = (uint64_t)ctx->cu_count * g * w;
-    uint32_t l = ceil_log2((m + 2 * resident - 1) / (2 * resident));
-    *log2B = std::min<uint32_t>(16, std::max<uint32_t>(8, l));
+    // Tile size by makespan: resident wave k runs tiles k, k + R, ... (R
+    // resident waves); tile 0 holds the zero prefix, whose whole rows are
+    // skipped; each tile adds a fixed cost (fix-up, partial) of about
+    // kTileCost blocks.  Ties go to the larger tile (fewer partials).
+    const uint64_t R = (uint64_t)ctx->cu_count * g * w;
+    constexpr uint64_t kTileCost = 64;
+    uint64_t best_cost = ~0ull;
+    uint32_t best_l = 16;
+    for (uint32_t l = 16; l >= 8; --l) {
+        const uint64_t B = 1ull << l;
+        const uint64_t T = (m + B - 1) / B;
+        const uint64_t z = T * B - m;
+        const uint64_t n0 = (T + R - 1) / R, n1 = T > 1 ? (T - 1 + R - 1) / R : 0;
+        const uint64_t c0 = (n0 - 1) * B + (B - z / 64 * 64) + kTileCost * n0;
+        const uint64_t c1 = n1 * (B + kTileCost);
+        const uint64_t cost = std::max(c0, c1);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best_l = l;
+        }
+    }
+    *log2B = best_l;
 }
 
 void gcm::message_shape(const gcm_ctx *ctx, uint32_t nr, uint64_t len, uint64_t aad_len, uint32_t *log2B,

@@ -84,7 +84,7 @@ extern "C" int gcm_autotune(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32
     if (e == hipSuccess)
         e = hipEventCreate(&ev1);
 
-    const uint32_t wave_opts[2] = {8, 16};
+    const uint32_t wave_opts[3] = {8, 12, 16};
     float best_ms = 1e30f;
     uint32_t best_l = 0, best_w = 0, tried = 0;
     bool all_equal = true;
@@ -212,7 +212,7 @@ extern "C" int gcm_autotune_load(gcm_ctx *ctx, const char *path)
         if (std::sscanf(text.c_str() + pos,
                         "{\"key_bytes\": %u, \"len_log2\": %u, \"log2_tile_blocks\": %u, \"waves\": %u}", &kb, &ll,
                         &lt, &wv) == 4 &&
-            (kb == 16 || kb == 24 || kb == 32) && ll < 64 && lt >= 6 && lt <= 20 && (wv == 8 || wv == 16)) {
+            (kb == 16 || kb == 24 || kb == 32) && ll < 64 && lt >= 6 && lt <= 20 && (wv == 8 || wv == 12 || wv == 16)) {
             ctx->tuned[(uint64_t)kb << 32 | ll] = {lt, wv};
             ++loaded;
         }

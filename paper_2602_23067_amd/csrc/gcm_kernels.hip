@@ -48,6 +48,15 @@ __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Workgroup barrier ordering LDS accesses only: a wave's outstanding global
+// or spill stores do not hold the other waves at the barrier.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Read-only device data (key slots, descriptors, work lists) is read through
 // the constant address space so uniform reads become scalar loads into SGPRs.
 #define CONST_AS __attribute__((address_space(4)))
@@ -328,11 +337,20 @@ __global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t
 {
     __shared__ uint32_t te0[256], sb[256];
     __shared__ uint32_t h_sh[4];
-    for (int i = threadIdx.x; i < 256; i += 64) {
-        te0[i] = te0g[i];
-        sb[i] = sbg[i];
+    {
+        uint32_t a[4], b[4];  // all eight loads in flight before the stores
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            a[r] = te0g[threadIdx.x + 64 * r];
+            b[r] = sbg[threadIdx.x + 64 * r];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            te0[threadIdx.x + 64 * r] = a[r];
+            sb[threadIdx.x + 64 * r] = b[r];
+        }
     }
-    __syncthreads();
+    lds_barrier();
     const KeyArg key = chunk.keys[blockIdx.x];
     KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(chunk.slots[blockIdx.x]);
     if (threadIdx.x == 0) {
@@ -348,7 +366,7 @@ __global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t
             h_sh[i] = h[i];
         }
     }
-    __syncthreads();
+    lds_barrier();
     // H^(2^k) = F_k(H): lane k applies its Frobenius table (F_0 is the identity)
     const int k = threadIdx.x;
     if (k < kPowLevels) {
@@ -431,12 +449,12 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
         if (tid == 0)
             m_sh = m;
     }
-    __syncthreads();
+    lds_barrier();
     if (tid < 128) {
         const uint32_t mm[4] = {m_sh.x, m_sh.y, m_sh.z, m_sh.w};
         basis[tid] = poly_to_mem(poly_mul_xi(mem_to_poly(mm), tid));
     }
-    __syncthreads();
+    lds_barrier();
     if (b == kTab4Levels) {
         u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab8Off);
         // entry-major: (byte value v at position k) * M at index 16*v + k
@@ -744,20 +762,22 @@ __device__ __forceinline__ u32x4 ghash_mul8(u32x4 a, u32x4 x, const uint8_t *__r
 {
     const u32x4 r = rot_bytes_lane(a, g);
     const uint32_t w[4] = {r.x, r.y, r.z, r.w};
-    u32x4 e[16];
+    u32x4 acc = x;
+    // two halves of eight lookups, so at most 32 result registers are live
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        // address = 256 * (byte j of r) + 16 * position
-        const uint32_t sel = 0x0c0c0000u | ((4u + (uint32_t)(j & 3)) << 8) | (uint32_t)(j & 3);
-        const uint32_t addr = __builtin_amdgcn_perm(w[j >> 2], g.pos[j >> 2], sel);
-        e[j] = *reinterpret_cast<const u32x4 *>(lds + addr);
+    for (int h = 0; h < 2; ++h) {
+        u32x4 e[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int j = 8 * h + q;
+            // address = 256 * (byte j of r) + 16 * position
+            const uint32_t sel = 0x0c0c0000u | ((4u + (uint32_t)(j & 3)) << 8) | (uint32_t)(j & 3);
+            const uint32_t addr = __builtin_amdgcn_perm(w[j >> 2], g.pos[j >> 2], sel);
+            e[q] = *reinterpret_cast<const u32x4 *>(lds + addr);
+        }
+        acc = xor3v(xor3v(e[0], e[1], e[2]), xor3v(e[3], e[4], e[5]), xor3v(e[6], e[7], acc));
     }
-    const u32x4 p0 = xor3v(e[0], e[1], e[2]);
-    const u32x4 p1 = xor3v(e[3], e[4], e[5]);
-    const u32x4 p2 = xor3v(e[6], e[7], e[8]);
-    const u32x4 p3 = xor3v(e[9], e[10], e[11]);
-    const u32x4 p4 = xor3v(e[12], e[13], e[14]);
-    return xor3v(xor3v(p0, p1, p2), xor3v(p3, p4, e[15]), x);
+    return acc;
 }
 
 // zero-padded load of block `blk` of a buffer of `total` bytes
@@ -939,10 +959,27 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         counters[0] = 0;  // reject count for this launch (read by the zero-fill)
 
     {
-        // T-tables: dword 16384 + 64*e + 16*t + c holds rotl(TE0[e], 8t)
-        uint32_t *w = reinterpret_cast<uint32_t *>(lds_v) + 16384;
-        for (int i = threadIdx.x; i < 16384; i += WAVES * 64)
-            w[i] = rotl32(te0g[i >> 6], 8 * ((i >> 4) & 3));
+        // T-tables: dword 16384 + 64*e + 16*t + c holds rotl(TE0[e], 8t); work
+        // item (e, t) writes the 16 copies of one entry, all loads issued first
+        constexpr int kPer = (1024 + WAVES * 64 - 1) / (WAVES * 64);
+        uint32_t v[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int q = (int)threadIdx.x + r * WAVES * 64;
+            v[r] = q < 1024 ? rotl32(te0g[q >> 2], 8 * (q & 3)) : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int q = (int)threadIdx.x + r * WAVES * 64;
+            if (q >= 1024)
+                break;
+            u32x4 *dst = lds_v + 4096 + 4 * q;  // dword 16384 + 64*(q >> 2) + 16*(q & 3)
+            const u32x4 x = {v[r], v[r], v[r], v[r]};
+            dst[0] = x;
+            dst[1] = x;
+            dst[2] = x;
+            dst[3] = x;
+        }
     }
     const LaneK lk = lane_constants(threadIdx.x & 63);
     const GhK gk = gh_constants(threadIdx.x & 63);
@@ -961,12 +998,23 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             first = it * WAVES;
         }
         if (d.slot != cur_slot) {
-            __syncthreads();
-            const u32x4 *src = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab8Off);
-            for (int i = threadIdx.x; i < 4096; i += WAVES * 64)
-                lds_v[i] = src[i];
+            lds_barrier();
+            const GLOBAL_AS u32x4 *src = gptr<const u32x4>(d.slot + kSlotTab8Off);
+            constexpr int kPer = (4096 + WAVES * 64 - 1) / (WAVES * 64);
+            u32x4 st[kPer];
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const uint32_t q = threadIdx.x + r * WAVES * 64;
+                st[r] = q < 4096u ? src[q] : u32x4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int r = 0; r < kPer; ++r) {
+                const uint32_t q = threadIdx.x + r * WAVES * 64;
+                if (q < 4096u)
+                    lds_v[q] = st[r];
+            }
             cur_slot = d.slot;
-            __syncthreads();
+            lds_barrier();
         }
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.n_tiles) {
@@ -1020,15 +1068,27 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         ++nbits;
     const bool horner = T > (uint64_t)kCombineThreads;
     {
-        const u32x4 *g = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off);
+        // all of a thread's table loads are issued before any is stored
+        const GLOBAL_AS u32x4 *g = gptr<const u32x4>(d.slot + kSlotTab4Off);
         const int ntab = 1 + (horner ? kCombineLog2 + 1 : nbits);
-        for (int e = (int)i; e < ntab * 512; e += kCombineThreads) {
+        constexpr int kPer = ((kCombineLog2 + 2) * 512 + kCombineThreads - 1) / kCombineThreads;
+        u32x4 st[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int e = (int)i + r * kCombineThreads;
             const int tix = e >> 9;
             const int lvl = tix == 0 ? 0 : (int)d.log2B + tix - 1;
-            tabs[tix][e & 511] = g[(uint64_t)lvl * 512 + (e & 511)];
+            if (e < ntab * 512)
+                st[r] = g[(uint64_t)lvl * 512 + (e & 511)];
+        }
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int e = (int)i + r * kCombineThreads;
+            if (e < ntab * 512)
+                tabs[e >> 9][e & 511] = st[r];
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     u32x4 acc = {0, 0, 0, 0};
     if (i < T) {
@@ -1060,7 +1120,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
     acc = wave_xor_reduce(acc);
     if ((i & 63) == 0)
         red[i >> 6] = acc;
-    __syncthreads();
+    lds_barrier();
     if (i == 0) {
         u32x4 s = red[0];
         for (int w = 1; w < kCombineThreads / 64; ++w)
@@ -1173,6 +1233,8 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
     switch (waves) {
     case 8:
         return launch_tiles_w<8>(descs, items, n_items, single, te0, p, counters, grid, s);
+    case 12:
+        return launch_tiles_w<12>(descs, items, n_items, single, te0, p, counters, grid, s);
     case 16:
         return launch_tiles_w<16>(descs, items, n_items, single, te0, p, counters, grid, s);
     default:
@@ -1187,6 +1249,9 @@ int max_groups_per_cu(int waves)
     switch (waves) {
     case 8:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false>, 8 * 64, 0);
+        break;
+    case 12:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<12, false>, 12 * 64, 0);
         break;
     case 16:
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false>, 16 * 64, 0);

@@ -83,7 +83,7 @@ def test_key_sizes(ctx, key_len):
     _check_case(ctx, key, iv, workloads.random_bytes(r, 33), workloads.random_bytes(r, 70001))
 
 
-@pytest.mark.parametrize("shape", [(6, 8, 1), (7, 16, 1), (9, 16, 1), (10, 8, 2), (12, 8, 3), (0, 0, 0)])
+@pytest.mark.parametrize("shape", [(6, 8, 1), (8, 12, 1), (7, 16, 1), (9, 16, 1), (10, 8, 2), (12, 8, 3), (0, 0, 0)])
 def test_geometry_invariance(ctx, shape):
     """The paper's geometry-agnostic counter map: identical bits for every launch shape."""
     r = workloads.rng_for(13)
