@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12  # LDS bytes per clock per CU x CUs x clock
 
 
 def parse():
@@ -436,6 +437,8 @@ def main():
     else:
         tiles = -(-blocks // (1 << log2B))
     tile_bytes = 2 * n + aad_len + 16 * tiles
+    nr = len(msg.key) // 4 + 6
+    lds_bytes_per_block = 4 * (1 + 4 + 16 * (nr - 3) + 16) + 16 * 16
     tile_gbs = tile_bytes / (tile_ms * 1e-3) / 1e9
 
     cpu = None
@@ -512,6 +515,19 @@ def main():
             "traffic": measured_traffic(tile_bytes) if (args.ny, args.nx) == (16384, 16384) else None,
             "tile_kernel_ms": round(tile_ms, 4),
             "algorithmic_bytes_per_launch": tile_bytes,
+        },
+        # the resource that binds the tile kernel: LDS reads of the AES T-tables
+        # (4 bytes per lane per lookup; 197 lookups per AES-256 block with
+        # counter-mode caching through round 2) and of the GHASH byte table
+        # (16 lookups of 16 bytes), against 128 B/clk/CU x 256 CUs x 2.4 GHz
+        "lds_roofline": {
+            "kernel": "k_gcm_tiles",
+            "bound": "lds",
+            "achieved": round(lds_bytes_per_block * blocks / (tile_ms * 1e-3) / 1e12, 2),
+            "peak": LDS_PEAK_TBS,
+            "unit": "TB/s",
+            "frac": round(lds_bytes_per_block * blocks / (tile_ms * 1e-3) / 1e12 / LDS_PEAK_TBS, 4),
+            "lds_bytes_per_block": lds_bytes_per_block,
         },
         "cpu_baseline": cpu,
         "batch_config3": batch3,

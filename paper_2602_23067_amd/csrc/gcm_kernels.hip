@@ -635,7 +635,9 @@ template <int R0, int NR>
 __device__ __forceinline__ u32x4 aes_rounds(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
                                             const CONST_AS uint32_t *rk, const uint8_t *lds, const LaneK &lk)
 {
-#pragma unroll
+    // rounds stay a loop: each depends on the last, and the smaller code
+    // measured slightly faster than the unrolled form
+#pragma unroll 1
     for (int r = R0; r < NR; ++r) {
         const uint32_t k0 = rotr_by(rk[4 * r + 0], lk.rot), k1 = rotr_by(rk[4 * r + 1], lk.rot);
         const uint32_t k2 = rotr_by(rk[4 * r + 2], lk.rot), k3 = rotr_by(rk[4 * r + 3], lk.rot);
