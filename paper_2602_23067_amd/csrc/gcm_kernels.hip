@@ -16,6 +16,7 @@
 //
 // No MFMA: the work is byte lookups and XORs, not a real-valued contraction.
 #include <hip/hip_runtime.h>
+#include <stddef.h>
 #include <stdint.h>
 
 #include "gcm_internal.h"
@@ -523,18 +524,6 @@ __device__ __forceinline__ u32x4 mul_tab4_wide(u32x4 a, const u32x4 *__restrict_
     return r;
 }
 
-// a * H^e for 0 <= e < 2^bits using the tables of H^(2^(level0 + k))
-__device__ __forceinline__ u32x4 mul_hpow(u32x4 a, uint64_t e, int bits, const uint8_t *slot, int level0)
-{
-    for (int k = 0; k < bits; ++k) {
-        const u32x4 *tab = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off + (uint64_t)(level0 + k) * kTab4Bytes);
-        const u32x4 m = mul_tab4(a, tab);
-        if ((e >> k) & 1)
-            a = m;
-    }
-    return a;
-}
-
 __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 {
 #pragma unroll
@@ -944,6 +933,19 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         }
     }
     a = wave_xor_reduce(a);
+    // lift by H^((T-1-t)*B), so that the reduce phase is a plain XOR: one
+    // wave-wide product per set bit of T-1-t, with H^(2^(log2B+k)) from the
+    // key header
+    {
+        const uint64_t j = d.n_tiles - 1 - t;
+        const CONST_AS uint32_t *hp = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot + offsetof(KeySlotHdr, hpow)));
+        for (uint32_t k = 0; (j >> k) != 0; ++k) {
+            if ((j >> k) & 1) {
+                const uint32_t lv = 4u * (d.log2B + k);
+                a = gf_mul_wave(a, u32x4{hp[lv], hp[lv + 1], hp[lv + 2], hp[lv + 3]});
+            }
+        }
+    }
     if (lane == 0)
         partials[d.tile_base + t] = a;
 }
@@ -1033,92 +1035,37 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
 // ---------------------------------------------------------------- combine + tag
 
 constexpr int kCombineThreads = 1024;
-constexpr int kCombineLog2 = 10;
 
-// S = sum_t p_t * H^((T-1-t)*B + 1); tag = S xor E_K(J0).  Thread i runs a
-// Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B),
-// lifts its value by H^((T-1-t_last)*B) through the exponent bits, and the
-// XOR over threads closes the tree; one more *H accounts for GHASH's final
-// multiplication.  The nibble tables this needs (at most 12 of 8 KiB) are
-// staged in LDS first, so every multiply is 32 LDS reads.  E_K(J0) was left
-// by the tile kernel right after the message's T partials.
+// S = sum_t P_t * H with P_t = p_t * H^((T-1-t)*B) as the tile kernel left
+// it, so the tree's remaining levels are an XOR across the workgroup; one
+// multiply by H (the nibble table of H staged in LDS) is GHASH's final
+// multiplication; tag = S xor E_K(J0), which the tile kernel left right after
+// the message's T partials.
 template <bool BATCH>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
 {
-    __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
+    __shared__ u32x4 tab_h[512];
     __shared__ u32x4 red[kCombineThreads / 64];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
-    const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
 
-    // the first eight partials of this thread, loaded ahead of the table staging
-    u32x4 pv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const uint64_t t = (uint64_t)i + (uint64_t)q * kCombineThreads;
-        pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
-    }
-
-    // exponent bits needed for T-1-t_last < min(T, 1024), and whether any
-    // thread owns more than one partial
-    const uint64_t span = T < (uint64_t)kCombineThreads ? T : (uint64_t)kCombineThreads;
-    int nbits = 0;
-    while (nbits < kCombineLog2 && (1ull << nbits) < span)
-        ++nbits;
-    const bool horner = T > (uint64_t)kCombineThreads;
-    {
-        // all of a thread's table loads are issued before any is stored
-        const GLOBAL_AS u32x4 *g = gptr<const u32x4>(d.slot + kSlotTab4Off);
-        const int ntab = 1 + (horner ? kCombineLog2 + 1 : nbits);
-        constexpr int kPer = ((kCombineLog2 + 2) * 512 + kCombineThreads - 1) / kCombineThreads;
-        u32x4 st[kPer];
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int e = (int)i + r * kCombineThreads;
-            const int tix = e >> 9;
-            const int lvl = tix == 0 ? 0 : (int)d.log2B + tix - 1;
-            if (e < ntab * 512)
-                st[r] = g[(uint64_t)lvl * 512 + (e & 511)];
-        }
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int e = (int)i + r * kCombineThreads;
-            if (e < ntab * 512)
-                tabs[e >> 9][e & 511] = st[r];
-        }
-    }
-    lds_barrier();
-
     u32x4 acc = {0, 0, 0, 0};
-    if (i < T) {
-        uint64_t t_last = i;
-        for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
-            if (t0 != i) {
+    for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
+        u32x4 pv[8];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
-                    pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
-                }
-            }
+        for (int q = 0; q < 8; ++q) {
+            const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+            pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+        }
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
-                if (t < T) {
-                    acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ pv[q];
-                    t_last = t;
-                }
-            }
-        }
-        const uint64_t e = T - 1 - t_last;
-        for (int k = 0; k < nbits; ++k) {
-            const u32x4 m = mul_tab4(acc, tabs[1 + k]);
-            if ((e >> k) & 1)
-                acc = m;
-        }
+        for (int q = 0; q < 8; ++q)
+            acc ^= pv[q];
     }
+    if (i < 512)
+        tab_h[i] = gptr<const u32x4>(d.slot + kSlotTab4Off)[i];
     acc = wave_xor_reduce(acc);
     if ((i & 63) == 0)
         red[i >> 6] = acc;
@@ -1127,7 +1074,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         u32x4 s = red[0];
         for (int w = 1; w < kCombineThreads / 64; ++w)
             s ^= red[w];
-        s = mul_tab4(s, tabs[0]);  // * H
+        s = mul_tab4(s, tab_h);  // * H
         const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         if (d.op == 0) {
