@@ -18,7 +18,7 @@ namespace gcm {
 // ---- key slot (device memory, one per resident key) ----
 constexpr int kMaxNr = 14;
 constexpr int kPowLevels = 48;      // H^(2^k), k = 0..47
-constexpr int kTab4Levels = 6;      // nibble tables for H^(2^k), k = 0..5 (fix-ups; level 0 is H)
+constexpr int kTab4Levels = 40;     // nibble tables for H^(2^k), k = 0..39
 constexpr int kStrideLevel = 6;     // the per-lane Horner multiplier is H^64 = H^(2^6)
 constexpr int kKeyChunk = 56;       // keys per key-setup launch (by-value kernel arguments)
 

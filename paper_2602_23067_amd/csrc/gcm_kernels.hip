@@ -16,7 +16,6 @@
 //
 // No MFMA: the work is byte lookups and XORs, not a real-valued contraction.
 #include <hip/hip_runtime.h>
-#include <stddef.h>
 #include <stdint.h>
 
 #include "gcm_internal.h"
@@ -48,6 +47,21 @@ __device__ __forceinline__ uint32_t byte_of(u32x4 a, int k)
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
 __device__ __forceinline__ uint32_t uniform(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// XOR of x over the 64 lanes of the wave, returned in every lane, without
+// going through the LDS (where a shuffle would queue behind table lookups):
+// DPP steps within each row of 16 lanes, then row swaps across the wave.
+__device__ __forceinline__ uint32_t wave_xor_u32(uint32_t x)
+{
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x140, 0xF, 0xF, false);  // row_mirror
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows 0<->1, 2<->3
+    x = p[0] ^ p[1];
+    const auto q = __builtin_amdgcn_permlane32_swap(x, x, false, false);  // rows 0,1 <-> 2,3
+    return q[0] ^ q[1];
+}
 
 // Workgroup barrier ordering LDS accesses only: a wave's outstanding global
 // or spill stores do not hold the other waves at the barrier.
@@ -412,15 +426,8 @@ __device__ u32x4 gf_mul_wave(u32x4 a, u32x4 b)
         acc.lo ^= t.lo;
         acc.hi ^= t.hi;
     }
-    u32x4 r = poly_to_mem(acc);
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        r.x ^= __shfl_xor(r.x, off, 64);
-        r.y ^= __shfl_xor(r.y, off, 64);
-        r.z ^= __shfl_xor(r.z, off, 64);
-        r.w ^= __shfl_xor(r.w, off, 64);
-    }
-    return r;
+    const u32x4 r = poly_to_mem(acc);
+    return u32x4{wave_xor_u32(r.x), wave_xor_u32(r.y), wave_xor_u32(r.z), wave_xor_u32(r.w)};
 }
 
 // Fixed-multiplier tables of one key (grid.y indexes the key).
@@ -526,14 +533,7 @@ __device__ __forceinline__ u32x4 mul_tab4_wide(u32x4 a, const u32x4 *__restrict_
 
 __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        a.x ^= __shfl_xor(a.x, off, 64);
-        a.y ^= __shfl_xor(a.y, off, 64);
-        a.z ^= __shfl_xor(a.z, off, 64);
-        a.w ^= __shfl_xor(a.w, off, 64);
-    }
-    return a;
+    return u32x4{wave_xor_u32(a.x), wave_xor_u32(a.y), wave_xor_u32(a.z), wave_xor_u32(a.w)};
 }
 
 // ---------------------------------------------------------------- fused tile kernel
@@ -933,19 +933,6 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         }
     }
     a = wave_xor_reduce(a);
-    // lift by H^((T-1-t)*B), so that the reduce phase is a plain XOR: one
-    // wave-wide product per set bit of T-1-t, with H^(2^(log2B+k)) from the
-    // key header
-    {
-        const uint64_t j = d.n_tiles - 1 - t;
-        const CONST_AS uint32_t *hp = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot + offsetof(KeySlotHdr, hpow)));
-        for (uint32_t k = 0; (j >> k) != 0; ++k) {
-            if ((j >> k) & 1) {
-                const uint32_t lv = 4u * (d.log2B + k);
-                a = gf_mul_wave(a, u32x4{hp[lv], hp[lv + 1], hp[lv + 2], hp[lv + 3]});
-            }
-        }
-    }
     if (lane == 0)
         partials[d.tile_base + t] = a;
 }
@@ -1035,37 +1022,92 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
 // ---------------------------------------------------------------- combine + tag
 
 constexpr int kCombineThreads = 1024;
+constexpr int kCombineLog2 = 10;
 
-// S = sum_t P_t * H with P_t = p_t * H^((T-1-t)*B) as the tile kernel left
-// it, so the tree's remaining levels are an XOR across the workgroup; one
-// multiply by H (the nibble table of H staged in LDS) is GHASH's final
-// multiplication; tag = S xor E_K(J0), which the tile kernel left right after
-// the message's T partials.
+// S = sum_t p_t * H^((T-1-t)*B + 1); tag = S xor E_K(J0).  Thread i runs a
+// Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B),
+// lifts its value by H^((T-1-t_last)*B) through the exponent bits, and the
+// XOR over threads closes the tree; one more *H accounts for GHASH's final
+// multiplication.  The nibble tables this needs (at most 12 of 8 KiB) are
+// staged in LDS first, so every multiply is 32 LDS reads.  E_K(J0) was left
+// by the tile kernel right after the message's T partials.
 template <bool BATCH>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
 {
-    __shared__ u32x4 tab_h[512];
+    __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
     __shared__ u32x4 red[kCombineThreads / 64];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
+    const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
 
-    u32x4 acc = {0, 0, 0, 0};
-    for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
-        u32x4 pv[8];
+    // the first eight partials of this thread, loaded ahead of the table staging
+    u32x4 pv[8];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
-            pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+    for (int q = 0; q < 8; ++q) {
+        const uint64_t t = (uint64_t)i + (uint64_t)q * kCombineThreads;
+        pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+    }
+
+    // exponent bits needed for T-1-t_last < min(T, 1024), and whether any
+    // thread owns more than one partial
+    const uint64_t span = T < (uint64_t)kCombineThreads ? T : (uint64_t)kCombineThreads;
+    int nbits = 0;
+    while (nbits < kCombineLog2 && (1ull << nbits) < span)
+        ++nbits;
+    const bool horner = T > (uint64_t)kCombineThreads;
+    {
+        // all of a thread's table loads are issued before any is stored
+        const GLOBAL_AS u32x4 *g = gptr<const u32x4>(d.slot + kSlotTab4Off);
+        const int ntab = 1 + (horner ? kCombineLog2 + 1 : nbits);
+        constexpr int kPer = ((kCombineLog2 + 2) * 512 + kCombineThreads - 1) / kCombineThreads;
+        u32x4 st[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const int e = (int)i + r * kCombineThreads;
+            const int tix = e >> 9;
+            const int lvl = tix == 0 ? 0 : (int)d.log2B + tix - 1;
+            if (e < ntab * 512)
+                st[r] = g[(uint64_t)lvl * 512 + (e & 511)];
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-            acc ^= pv[q];
+        for (int r = 0; r < kPer; ++r) {
+            const int e = (int)i + r * kCombineThreads;
+            if (e < ntab * 512)
+                tabs[e >> 9][e & 511] = st[r];
+        }
     }
-    if (i < 512)
-        tab_h[i] = gptr<const u32x4>(d.slot + kSlotTab4Off)[i];
+    lds_barrier();
+
+    u32x4 acc = {0, 0, 0, 0};
+    if (i < T) {
+        uint64_t t_last = i;
+        for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
+            if (t0 != i) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+                    pv[q] = t < T ? partials[d.tile_base + t] : u32x4{0, 0, 0, 0};
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
+                if (t < T) {
+                    acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ pv[q];
+                    t_last = t;
+                }
+            }
+        }
+        const uint64_t e = T - 1 - t_last;
+        for (int k = 0; k < nbits; ++k) {
+            const u32x4 m = mul_tab4(acc, tabs[1 + k]);
+            if ((e >> k) & 1)
+                acc = m;
+        }
+    }
     acc = wave_xor_reduce(acc);
     if ((i & 63) == 0)
         red[i >> 6] = acc;
@@ -1074,7 +1116,7 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         u32x4 s = red[0];
         for (int w = 1; w < kCombineThreads / 64; ++w)
             s ^= red[w];
-        s = mul_tab4(s, tab_h);  // * H
+        s = mul_tab4(s, tabs[0]);  // * H
         const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         if (d.op == 0) {
