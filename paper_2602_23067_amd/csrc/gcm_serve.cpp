@@ -260,8 +260,11 @@ static void worker_main(gcm_serve *s)
         if (s->stopping && inflight == 0 && s->policy.pending() == 0 && s->policy.ready() == 0)
             break;
         if (inflight) {
+            // poll without sleeping while batches are on the GPU: a timed
+            // sleep rounds up to the kernel's timer slack (~50 us), which
+            // would add that much to every request's latency
             lk.unlock();
-            std::this_thread::sleep_for(std::chrono::microseconds(10));
+            std::this_thread::yield();
             lk.lock();
         } else {
             s->cv_work.wait_for(lk, std::chrono::milliseconds(2));
