@@ -1039,7 +1039,6 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
     __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
     __shared__ u32x4 red[kCombineThreads / 64];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
-    const uint8_t *slot = reinterpret_cast<const uint8_t *>(d.slot);
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
 
