@@ -92,7 +92,7 @@ extern "C" int gcm_autotune(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32
     bool have_ref = false;
     const bool save_prof = ctx->prof;
     ctx->prof = false;
-    for (uint32_t l = 8; l <= 14 && e == hipSuccess && rc == GCM_OK; ++l) {
+    for (uint32_t l = 8; l <= 16 && e == hipSuccess && rc == GCM_OK; ++l) {
         if ((1ull << l) > 4 * m && l > 8)
             break;  // tiles larger than the whole message add nothing
         for (uint32_t w : wave_opts) {
