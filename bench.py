@@ -339,9 +339,9 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(a single message shards by block range with one 16-byte partial per GPU; "
-              "see the design notes)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(a single message would shard by block range with one 16-byte partial per GPU)",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
