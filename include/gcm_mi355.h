@@ -138,6 +138,60 @@ int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, siz
                              const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
                              uint64_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------- counter mode only, GMAC */
+
+/* AES-CTR without authentication (the paper's CTR-only baseline, the "E2E CTR"
+ * column of its GCM-vs-CTR comparison table; "Choice of Cryptographic Mode").
+ * out_d = in_d XOR keystream, where data block i (0-based) uses counter
+ * inc32^(i+1)(J0) with J0 = IV || 0^31 || 1: the GCTR step of SP 800-38D
+ * GCM-AE, so out_d equals gcm_encrypt's ciphertext and the same call
+ * decrypts.  No tag, no workspace.  key, iv: host; in_d, out_d: device
+ * (len bytes, 16-byte aligned, in_d == out_d allowed).  Blocks until the
+ * output is written (the key may come from the context's key cache). */
+int gcm_ctr_xcrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                   const uint8_t *in_d, uint64_t len, uint8_t *out_d, void *stream);
+
+/* gcm_ctr_xcrypt with a registered key slot, enqueued on `stream` without
+ * host synchronisation. */
+int gcm_ctr_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *in_d, uint64_t len,
+                  uint8_t *out_d, void *stream);
+
+/* GMAC (SP 800-38D: GCM-AE with an empty plaintext): tag_out (host, 16 B) =
+ * GHASH_H(A || 0-pad || [8|A|]_64 || 0^64) XOR E_K(J0) over aad_d (device,
+ * aad_len bytes, 16-byte aligned).  Runs only the GHASH map and reduce
+ * phases (the scope of the paper's GHASH-only throughput table); whole rows
+ * of AAD blocks take no AES work.  Blocks until the tag is on the host. */
+int gcm_gmac(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+             const uint8_t *aad_d, uint64_t aad_len, uint8_t tag_out[16], void *stream);
+
+/* ---------------------------------------------------------------- host-to-host pipeline */
+
+/* gcm_encrypt / gcm_decrypt_verify on HOST buffers (the paper's
+ * "Asynchronous Streams Pipeline" and "Optimized Memory Pipeline":
+ * page-locked host memory and concurrent streams overlapping PCIe transfers
+ * with the kernels).  The message moves through a ring of three device chunk
+ * buffers: the host-to-device copy of chunk c+1, the fused tile kernel on
+ * chunk c and the device-to-host copy of chunk c-1 run concurrently on three
+ * streams of the context; one combine after the last chunk forms the tag, so
+ * results are bit-identical to the device-resident calls.  aad_h, pt_h/ct_h
+ * and the outputs are host pointers (any alignment); pass page-locked memory
+ * (hipHostMalloc, torch pin_memory) for the copies to overlap, pageable
+ * memory works but serialises.  in == out is allowed.  Decrypt-verify writes
+ * plaintext chunks as they are done and zero-fills the whole output before
+ * returning when the tag does not match (accept 0).  Blocking.  If a HIP
+ * error occurs after copies started, the output may be partly written. */
+int gcm_encrypt_host(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                     const uint8_t *aad_h, uint64_t aad_len, const uint8_t *pt_h, uint64_t len, uint8_t *ct_h,
+                     uint8_t tag_out[16]);
+int gcm_decrypt_verify_host(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                            const uint8_t *aad_h, uint64_t aad_len, const uint8_t *ct_h, uint64_t len,
+                            const uint8_t tag[16], uint8_t *pt_h, int *accept);
+
+/* Chunk size of the host pipeline in bytes (rounded down to whole wave tiles,
+ * at least one tile); 0 restores the default of 64 MiB.  Three chunk buffers
+ * are allocated from the context's budget on first use.  4 KiB..16 GiB. */
+int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One message of a batch.  All offsets are byte offsets into one device

@@ -140,6 +140,7 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
     ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
     ctx_free(ctx, ctx->d_io, 256);
     ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+    pipeline_release(ctx);
     for (auto &pr : ctx->prof_pending) {
         (void)hipEventDestroy(pr.first);
         (void)hipEventDestroy(pr.second);
@@ -252,7 +253,7 @@ extern "C" int gcm_key_release(gcm_ctx *ctx, uint32_t slot)
 // one-shot path: look the key up in the cache, expand it on a miss (LRU eviction
 // among cache-owned slots only; the one-shot calls synchronise before
 // returning, so an evicted slot has no work in flight)
-static int cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot, hipStream_t s)
+int gcm::cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot, hipStream_t s)
 {
     std::string k(reinterpret_cast<const char *>(key), key_len);
     auto it = ctx->cache.find(k);
@@ -344,6 +345,8 @@ void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, ui
     const uint64_t B = 1ull << log2B;
     d->n_tiles = (d->m + B - 1) / B;
     d->z = d->n_tiles * B - d->m;
+    d->tile_lo = 0;
+    d->tile_hi = d->n_tiles;
     d->tile_base = tile_base;
     for (int i = 0; i < 3; ++i)
         d->iv[i] = (uint32_t)iv[4 * i] | ((uint32_t)iv[4 * i + 1] << 8) | ((uint32_t)iv[4 * i + 2] << 16) |
@@ -379,20 +382,36 @@ uint64_t gcm::workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs)
     return workspace_counter_bytes(n_msgs) + 16 * (total_tiles + n_msgs);
 }
 
-// Enqueue the kernels for one message on `s`.
-int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
+// Enqueue the tile kernel for tiles [d.tile_lo, d.tile_hi) of one message on `s`.
+int gcm::launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
 {
-    uint32_t *counters = reinterpret_cast<uint32_t *>(ws);
-    uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1);
-    const uint32_t items = d.groups;
+    uint32_t *counters = ws ? reinterpret_cast<uint32_t *>(ws) : nullptr;
+    uint8_t *partials = ws ? reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1) : nullptr;
+    const uint64_t tiles = d.tile_hi - d.tile_lo;
+    const uint32_t items = (uint32_t)((tiles + waves - 1) / waves);
+    if (items == 0)
+        return GCM_OK;
     const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(items, (uint32_t)ctx->cu_count * gpc));
     hipError_t e = prof_begin(ctx, s);
     if (e == hipSuccess)
         e = launch_tiles((int)waves, nullptr, nullptr, items, &d, ctx->d_tables, partials, counters, grid, s);
     if (e == hipSuccess)
         e = prof_end(ctx, s);
-    if (e == hipSuccess)
-        e = launch_combine(nullptr, 1, &d, partials, counters, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "tile kernel launch");
+    return GCM_OK;
+}
+
+// Enqueue the kernels for one message on `s`: tiles, then (GCM only) the
+// combine and, for decrypt-verify, the zero-fill of a rejected output.
+int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
+{
+    int rc = launch_tile_range(ctx, d, waves, gpc, ws, s);
+    if (rc || d.op == 2)
+        return rc;
+    uint32_t *counters = reinterpret_cast<uint32_t *>(ws);
+    uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1);
+    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, s);
     if (e == hipSuccess && d.op == 1) {
         const uint64_t chunks = (d.len / 16 + 255) / 256;
         const uint32_t zgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 4096));
@@ -421,8 +440,7 @@ extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_
     return workspace_bytes_for(T, 1);
 }
 
-// ensure the context's one-shot workspace holds `bytes` (caller holds ctx->mu)
-static int ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes)
+int gcm::ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes)
 {
     if (ctx->ws_bytes >= bytes)
         return GCM_OK;
@@ -560,6 +578,82 @@ extern "C" int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_l
                                   const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream)
 {
     return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream);
+}
+
+// ---------------------------------------------------------------- counter mode only, GMAC
+
+static int ctr_common(gcm_ctx *ctx, uint32_t slot, uint32_t nr, const uint8_t *iv, const uint8_t *in_d, uint64_t len,
+                      uint8_t *out_d, hipStream_t s)
+{
+    uint32_t log2B, waves, gpc;
+    message_shape(ctx, nr, len, 0, &log2B, &waves, &gpc);
+    MsgDesc d;
+    fill_desc(&d, 2, iv, 0, 0, (uint64_t)in_d, (uint64_t)out_d, len, 0, 0,
+              (uint64_t)(ctx->d_slots + kSlotBytes * slot), nr, log2B, waves, 0);
+    return launch_single(ctx, d, waves, gpc, nullptr, s);
+}
+
+static int check_ctr_args(const void *iv, size_t iv_len, const uint8_t *in_d, uint64_t len, const uint8_t *out_d)
+{
+    if (!iv)
+        return fail(GCM_E_ARG, "NULL argument");
+    if (iv_len != 12)
+        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    return check_message(0, len, nullptr, in_d, out_d);
+}
+
+extern "C" int gcm_ctr_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *in_d,
+                             uint64_t len, uint8_t *out_d, void *stream)
+{
+    if (!ctx)
+        return fail(GCM_E_ARG, "NULL argument");
+    int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
+    if (rc)
+        return rc;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipSetDevice");
+    return ctr_common(ctx, slot, ctx->slot_nr[slot], iv, in_d, len, out_d, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int gcm_ctr_xcrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                              const uint8_t *in_d, uint64_t len, uint8_t *out_d, void *stream)
+{
+    if (!ctx || !key)
+        return fail(GCM_E_ARG, "NULL argument");
+    if (!valid_key_len(key_len))
+        return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
+    int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
+    if (rc)
+        return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipSetDevice");
+    uint32_t slot;
+    rc = cached_slot_locked(ctx, key, key_len, &slot, s);
+    if (rc)
+        return rc;
+    rc = ctr_common(ctx, slot, slot_nr(key_len), iv, in_d, len, out_d, s);
+    if (rc)
+        return rc;
+    // like the other one-shot calls, return with the work done, so that the
+    // cached key slot may be reused by the next call on any stream
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return fail_hip(e, "hipStreamSynchronize");
+    return GCM_OK;
+}
+
+extern "C" int gcm_gmac(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                        const uint8_t *aad_d, uint64_t aad_len, uint8_t tag_out[16], void *stream)
+{
+    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, nullptr, 0, nullptr, nullptr, tag_out, nullptr,
+                   stream);
 }
 
 // ---------------------------------------------------------------- measurement

@@ -38,6 +38,18 @@ struct gcm_ctx {
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_free;
+    // host-to-host pipeline (created on first use): streams for H2D, the
+    // kernels and D2H, a ring of device chunk buffers and their events
+    uint64_t pipe_chunk = 0;  // requested chunk bytes (0 = default)
+    bool pipe_ready = false;
+    hipStream_t pipe_h2d = nullptr, pipe_comp = nullptr, pipe_d2h = nullptr;
+    static constexpr int kPipeBufs = 3;
+    hipEvent_t pipe_in[kPipeBufs] = {}, pipe_done[kPipeBufs] = {}, pipe_free[kPipeBufs] = {};
+    bool pipe_used[kPipeBufs] = {};
+    uint8_t *pipe_buf[kPipeBufs] = {};
+    uint64_t pipe_buf_bytes = 0;
+    uint8_t *pipe_aad = nullptr;
+    uint64_t pipe_aad_bytes = 0;
     std::mutex mu;
 };
 
@@ -70,6 +82,14 @@ int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void 
 uint64_t workspace_counter_bytes(uint64_t n_msgs);
 uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
 int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
+// release the host pipeline's streams, events and buffers (gcm_ctx_destroy)
+void pipeline_release(gcm_ctx *ctx);
+// ensure the context's one-shot workspace holds `bytes` (caller holds ctx->mu)
+int ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes);
+// one-shot key cache lookup / expansion (caller holds ctx->mu)
+int cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot, hipStream_t s);
+// tile kernel only, for tiles [d.tile_lo, d.tile_hi); ws may be NULL for op 2
+int launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
 // bracket the next tile launch with events when profiling is on (caller holds ctx->mu)
 hipError_t prof_begin(gcm_ctx *ctx, hipStream_t s);
 hipError_t prof_end(gcm_ctx *ctx, hipStream_t s);

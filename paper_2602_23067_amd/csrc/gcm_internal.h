@@ -61,8 +61,10 @@ struct MsgDesc {
     uint64_t z;        // zero-block left padding
     uint64_t tile_base;  // first wave tile of this message in the partials array
     uint64_t n_tiles;    // T
+    uint64_t tile_lo;    // this launch covers message tiles [tile_lo, tile_hi)
+    uint64_t tile_hi;    //   (0 and T except for chunked host-pipeline launches)
     uint32_t iv[3];      // IV as memory-order dwords
-    uint32_t op;         // 0 encrypt, 1 decrypt-verify
+    uint32_t op;         // 0 encrypt, 1 decrypt-verify, 2 CTR only (no GHASH, no tag)
     uint32_t log2B;      // wave tile = 2^log2B blocks (>= 6)
     uint32_t nr;         // AES rounds
     uint32_t groups;     // workgroup items for this message

@@ -821,8 +821,9 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // blocks, lane l on block 64*r + l, so every load/store instruction moves one
 // contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
 // p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
-// across the wave.
-template <int NR>
+// across the wave.  With GH false the tile is counter mode only (no GHASH,
+// no partial).
+template <int NR, bool GH>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
                           const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
 {
@@ -840,7 +841,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         c.rk3 = rk[3];
     }
 
-    if (t == 0) {
+    if (GH && t == 0) {
         // E_K(J0) is the keystream block of counter value 1; the wave that owns
         // tile 0 leaves it after the message's partials for the combine
         const u32x4 ek = aes_ctr<NR>(1u, c, rk, lds, lk);
@@ -853,6 +854,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     const int64_t vbase = (int64_t)(t * B) - (int64_t)d.z;  // GHASH index of lane 0, row 0
     const uint32_t r0 = vbase < 0 ? (uint32_t)((uint64_t)(-vbase) >> 6) : 0u;
     const int64_t na = (int64_t)d.na;
+    const int64_t nafull = (int64_t)(d.aad_len >> 4);
     const int64_t nfull = (int64_t)(d.len >> 4);
     const int64_t ndat = (int64_t)d.n;
     const bool enc = d.op == 0;
@@ -860,6 +862,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     uint8_t *__restrict__ out = reinterpret_cast<uint8_t *>(d.out);
     const GLOBAL_AS u32x4 *in_g = gptr<const u32x4>(d.in);
     GLOBAL_AS u32x4 *out_g = gptr<u32x4>(d.out);
+    const GLOBAL_AS u32x4 *aad_g = gptr<const u32x4>(d.aad);
 
     u32x4 a = {0, 0, 0, 0};
     uint32_t hc = 0xffffffffu;  // upper counter bits `cur` belongs to (none yet)
@@ -894,28 +897,35 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             const u32x4 ks = aes_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
             const u32x4 o = x ^ ks;
             __builtin_nontemporal_store(o, out_g + j);
-            a = ghash_mul8(a, enc ? o : x, lds, gk);
+            if (GH)
+                a = ghash_mul8(a, enc ? o : x, lds, gk);
+        } else if (GH && v0 >= 0 && v0 + 64 <= nafull) {
+            // all 64 lanes hold whole AAD blocks: GHASH only
+            a = ghash_mul8(a, aad_g[(uint64_t)v0 + (uint64_t)lane], lds, gk);
         } else {
             // boundary row: zero padding, AAD, partial blocks or the length block
             const int64_t v = v0 + lane;
             const uint64_t j = (uint64_t)(v - na);
             const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
             u32x4 X = {0, 0, 0, 0};
-            if (v >= 0 && v < na) {
+            if (GH && v >= 0 && v < na) {
                 X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
             } else if (v >= na && v < na + ndat) {
                 const u32x4 x = load_block_partial(in, j, d.len);
                 const u32x4 o = x ^ ks;
                 store_block_partial(out, j, d.len, o);
                 X = enc ? mask_block(o, j, d.len) : x;
-            } else if (v == na + ndat) {
+            } else if (GH && v == na + ndat) {
                 const uint64_t abits = d.aad_len * 8, cbits = d.len * 8;
                 X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
                           bswap32((uint32_t)cbits)};
             }
-            a = ghash_mul8(a, X, lds, gk);
+            if (GH)
+                a = ghash_mul8(a, X, lds, gk);
         }
     }
+    if (!GH)
+        return;
 
     // fix-up: a * H^(63 - lane).  Messages whose key tables are shared by many
     // tiles use one multiply with that lane's table; others walk the exponent
@@ -937,7 +947,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         partials[d.tile_base + t] = a;
 }
 
-template <int WAVES, bool BATCH>
+template <int WAVES, bool BATCH, bool GH>
 __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restrict__ descs,
                                                           const WorkItem *__restrict__ items, uint32_t n_items,
                                                           MsgDesc single, const uint32_t *__restrict__ te0g,
@@ -946,7 +956,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
     __shared__ u32x4 lds_v[8192];  // 128 KiB: GHASH table, then the replicated T-tables
     const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
 
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (GH && blockIdx.x == 0 && threadIdx.x == 0)
         counters[0] = 0;  // reject count for this launch (read by the zero-fill)
 
     {
@@ -972,6 +982,10 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             dst[3] = x;
         }
     }
+    // with GHASH, the table staging of the first work item below starts and
+    // ends with a barrier, which also publishes the T-tables
+    if (!GH)
+        lds_barrier();
     const LaneK lk = lane_constants(threadIdx.x & 63);
     const GhK gk = gh_constants(threadIdx.x & 63);
 
@@ -986,9 +1000,9 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             first = w.first_tile;
         } else {
             d = single;
-            first = it * WAVES;
+            first = (uint32_t)d.tile_lo + it * WAVES;
         }
-        if (d.slot != cur_slot) {
+        if (GH && d.slot != cur_slot) {
             lds_barrier();
             const GLOBAL_AS u32x4 *src = gptr<const u32x4>(d.slot + kSlotTab8Off);
             constexpr int kPer = (4096 + WAVES * 64 - 1) / (WAVES * 64);
@@ -1008,13 +1022,13 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             lds_barrier();
         }
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
-        if (t < d.n_tiles) {
+        if (t < d.tile_hi) {
             if (d.nr == 10)
-                wave_tile<10>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<10, GH>(d, t, lds, lk, gk, te0g, partials);
             else if (d.nr == 12)
-                wave_tile<12>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<12, GH>(d, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile<14>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<14, GH>(d, t, lds, lk, gk, te0g, partials);
         }
     }
 }
@@ -1207,10 +1221,13 @@ static hipError_t launch_tiles_w(const MsgDesc *descs, const WorkItem *items, ui
                                  hipStream_t s)
 {
     if (descs)
-        hipLaunchKernelGGL((k_gcm_tiles<WAVES, true>), dim3(grid), dim3(WAVES * 64), 0, s, descs, items, n_items,
-                           MsgDesc{}, te0, partials, counters);
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, true, true>), dim3(grid), dim3(WAVES * 64), 0, s, descs, items,
+                           n_items, MsgDesc{}, te0, partials, counters);
+    else if (single->op == 2)
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, false>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
+                           n_items, *single, te0, partials, counters);
     else
-        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, true>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
                            n_items, *single, te0, partials, counters);
     return hipGetLastError();
 }
@@ -1238,13 +1255,13 @@ int max_groups_per_cu(int waves)
     hipError_t e = hipErrorInvalidValue;
     switch (waves) {
     case 8:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false>, 8 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false, true>, 8 * 64, 0);
         break;
     case 12:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<12, false>, 12 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<12, false, true>, 12 * 64, 0);
         break;
     case 16:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false>, 16 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false, true>, 16 * 64, 0);
         break;
     }
     return (e == hipSuccess && n > 0) ? n : 1;

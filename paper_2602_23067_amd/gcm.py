@@ -137,6 +137,12 @@ def load() -> ctypes.CDLL:
         "gcm_autotune_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
         "gcm_profile_read": ([vp, ctypes.POINTER(u64), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+        "gcm_ctr_xcrypt": ([vp, vp, sz, vp, sz, vp, u64, vp, vp], ctypes.c_int),
+        "gcm_ctr_async": ([vp, u32, vp, sz, vp, u64, vp, vp], ctypes.c_int),
+        "gcm_gmac": ([vp, vp, sz, vp, sz, vp, u64, vp, vp], ctypes.c_int),
+        "gcm_encrypt_host": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp], ctypes.c_int),
+        "gcm_decrypt_verify_host": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, i32p], ctypes.c_int),
+        "gcm_set_pipeline": ([vp, u64], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -179,6 +185,31 @@ def _stream(stream) -> int:
 
 def _host(b: bytes) -> ctypes.Array:
     return ctypes.create_string_buffer(bytes(b), len(b))
+
+
+def _hostbuf(t):
+    """(address, bytes) of a contiguous host uint8 buffer: a CPU torch tensor
+    (pinned or not) or a numpy array; (0, 0) for None/empty."""
+    if t is None:
+        return 0, 0
+    try:
+        import torch
+
+        if isinstance(t, torch.Tensor):
+            if t.is_cuda:
+                raise ValueError("host-pipeline buffers must be in host memory")
+            if t.dtype != torch.uint8 or not t.is_contiguous():
+                raise TypeError("host buffers must be contiguous uint8")
+            return (t.data_ptr() if t.numel() else 0), t.numel()
+    except ImportError:
+        pass
+    import numpy as np
+
+    if isinstance(t, np.ndarray):
+        if t.dtype != np.uint8 or not t.flags["C_CONTIGUOUS"]:
+            raise TypeError("host buffers must be contiguous uint8")
+        return (t.ctypes.data if t.size else 0), t.size
+    raise TypeError("expected a CPU torch.Tensor or a numpy array")
 
 
 class Context:
@@ -245,6 +276,49 @@ class Context:
         _check(load().gcm_decrypt_verify(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
                                          0 if aad is None else aad.numel(), _dev(ct), ct.numel(), _host(tag),
                                          _dev(pt), ctypes.byref(acc), _stream(stream)))
+        return acc.value == 1
+
+    # -------------------------------------------------------- counter mode only, GMAC
+    def ctr_xcrypt(self, key: bytes, iv: bytes, src, dst, stream=None) -> None:
+        """AES-CTR with GCM's counters (no tag); encrypts and decrypts."""
+        _check(load().gcm_ctr_xcrypt(self._h, _host(key), len(key), _host(iv), len(iv), _dev(src), src.numel(),
+                                     _dev(dst), _stream(stream)))
+
+    def ctr_async(self, slot: int, iv: bytes, src, dst, stream=None) -> None:
+        _check(load().gcm_ctr_async(self._h, slot, _host(iv), len(iv), _dev(src), src.numel(), _dev(dst),
+                                    _stream(stream)))
+
+    def gmac(self, key: bytes, iv: bytes, aad, stream=None) -> bytes:
+        """GMAC tag over the device buffer `aad` (GCM with an empty plaintext)."""
+        tag = ctypes.create_string_buffer(16)
+        _check(load().gcm_gmac(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
+                               0 if aad is None else aad.numel(), tag, _stream(stream)))
+        return tag.raw
+
+    # -------------------------------------------------------- host-to-host pipeline
+    def set_pipeline(self, chunk_bytes: int = 0) -> None:
+        _check(load().gcm_set_pipeline(self._h, chunk_bytes))
+
+    def encrypt_host(self, key: bytes, iv: bytes, aad, pt, ct) -> bytes:
+        """GCM-AE on host buffers (CPU tensors, ideally pinned, or numpy arrays)."""
+        a, alen = _hostbuf(aad)
+        p, plen = _hostbuf(pt)
+        c, clen = _hostbuf(ct)
+        if clen != plen:
+            raise ValueError("pt and ct must have the same length")
+        tag = ctypes.create_string_buffer(16)
+        _check(load().gcm_encrypt_host(self._h, _host(key), len(key), _host(iv), len(iv), a, alen, p, plen, c, tag))
+        return tag.raw
+
+    def decrypt_verify_host(self, key: bytes, iv: bytes, aad, ct, tag: bytes, pt) -> bool:
+        a, alen = _hostbuf(aad)
+        c, clen = _hostbuf(ct)
+        p, plen = _hostbuf(pt)
+        if clen != plen:
+            raise ValueError("ct and pt must have the same length")
+        acc = ctypes.c_int(-1)
+        _check(load().gcm_decrypt_verify_host(self._h, _host(key), len(key), _host(iv), len(iv), a, alen, c, clen,
+                                              _host(tag), p, ctypes.byref(acc)))
         return acc.value == 1
 
     # -------------------------------------------------------- async, resident key
