@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--dec-files", type=int, default=1024)
     ap.add_argument("--dec-side", type=int, default=4096)
     ap.add_argument("--skip-serving", action="store_true", help="skip the serving loop (config 5)")
+    ap.add_argument("--skip-modes", action="store_true",
+                    help="skip the CTR-only, GHASH-only (GMAC) and host-to-host pipeline measurements")
+    ap.add_argument("--e2e-iters", type=int, default=3)
     ap.add_argument("--serve-docs", type=int, default=256)
     ap.add_argument("--serve-reqs", type=int, default=3000)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -335,6 +338,66 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
     }
 
 
+def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag_d, ws, timed):
+    """The paper's other measurement scopes on the config-2 buffer: GCM vs
+    counter mode only (both with a resident key, tile-kernel events around
+    each), GHASH only (GMAC over the buffer taken as AAD: no AES work on whole
+    AAD rows), and host-to-host GCM through the chunked pinned-memory
+    pipeline against the device-resident kernel time."""
+    n = pt_d.numel()
+    slot = ctx.key_register(msg.key, stream)
+    gcm_tag = tag_d.clone()
+    try:
+        ms_gcm, tile_gcm = timed(lambda: ctx.encrypt_async(slot, msg.iv, aad_d, pt_d, ct_d, tag_d, ws, stream),
+                                 args.steps, 2)
+        ms_ctr, tile_ctr = timed(lambda: ctx.ctr_async(slot, msg.iv, pt_d, back_d, stream), args.steps, 2)
+        torch.cuda.synchronize()
+        ctr_same = bool(torch.equal(back_d, ct_d))
+        assert ws.numel() >= ctx.workspace_size(0, n)
+        mac_d = torch.zeros(16, dtype=torch.uint8, device=pt_d.device)
+        ms_mac, tile_mac = timed(lambda: ctx.encrypt_async(slot, msg.iv, pt_d, None, None, mac_d, ws, stream),
+                                 args.steps, 2)
+    finally:
+        torch.cuda.synchronize()
+        ctx.key_release(slot)
+
+    # host-to-host through the pipeline, pinned buffers, default 64 MiB chunks
+    pt_h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    pt_h.copy_(pt_d)
+    ct_h = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+    aad_h = aad_d.cpu().pin_memory()
+    ctx.encrypt_host(msg.key, msg.iv, aad_h, pt_h, ct_h)  # warm-up: buffers, streams
+    times = []
+    tag_h = None
+    for _ in range(max(1, args.e2e_iters)):
+        t = time.perf_counter()
+        tag_h = ctx.encrypt_host(msg.key, msg.iv, aad_h, pt_h, ct_h)
+        times.append(time.perf_counter() - t)
+    ms_e2e = 1e3 * sorted(times)[len(times) // 2]
+    same_tag = tag_h == bytes(gcm_tag.cpu().numpy().tobytes())
+    del pt_h, ct_h
+    return {
+        "workload": "the config-2 buffer (1 GiB FITS-shaped, AES-256, same key and IV), resident key",
+        "gcm_ms": round(ms_gcm, 4),
+        "gcm_tile_kernel_ms": round(tile_gcm, 4),
+        "ctr_only_ms": round(ms_ctr, 4),
+        "ctr_only_tile_kernel_ms": round(tile_ctr, 4),
+        "ctr_only_gbs": round(n / (ms_ctr * 1e-3) / 1e9, 2),
+        "gcm_over_ctr": round(ms_gcm / ms_ctr, 3),
+        "ctr_output_equals_gcm_ciphertext": ctr_same,
+        "ghash_only_gmac_ms": round(ms_mac, 4),
+        "ghash_only_gmac_gbs": round(n / (ms_mac * 1e-3) / 1e9, 2),
+        "e2e_host_pinned": {
+            "scope": "host-to-host GCM-AE: H2D + tile kernel + D2H over 64 MiB chunks on three streams, + combine",
+            "ms": round(ms_e2e, 3),
+            "gbs": round(n / (ms_e2e * 1e-3) / 1e9, 2),
+            "kernel_only_ms": round(ms_gcm, 4),
+            "kernel_share": round(ms_gcm / ms_e2e, 4),
+            "tag_identical_to_device_path": same_tag,
+        },
+    }
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -411,6 +474,11 @@ def main():
     ms_dec, tile_ms_dec = timed(dec_step, max(1, args.steps // 2), 2)
     accepted = int(ok_d.cpu()[0]) == 1
     same = bool(torch.equal(back_d, pt_d))
+
+    modes = None
+    if not args.skip_modes:
+        print("[bench] CTR-only, GHASH-only and host-pipeline modes", file=sys.stderr, flush=True)
+        modes = run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag_d, ws, timed)
 
     # one-shot latency of a 1 MiB AES-128 message (host-synchronous call)
     m1 = workloads.config1()
@@ -530,6 +598,7 @@ def main():
             "lds_bytes_per_block": lds_bytes_per_block,
         },
         "cpu_baseline": cpu,
+        "modes_config2": modes,
         "batch_config3": batch3,
         "decrypt_batch_config4": dec4,
         "serving_config5": serve5,

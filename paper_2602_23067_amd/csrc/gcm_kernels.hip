@@ -822,8 +822,10 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
 // p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
 // across the wave.  With GH false the tile is counter mode only (no GHASH,
-// no partial).
-template <int NR, bool GH>
+// no partial).  AADROWS adds a GHASH-only pass over rows of whole AAD blocks
+// (it costs the main loop its batching of LDS reads, so it is only compiled
+// into a kernel variant of its own).
+template <int NR, bool GH, bool AADROWS>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
                           const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
 {
@@ -865,9 +867,50 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     const GLOBAL_AS u32x4 *aad_g = gptr<const u32x4>(d.aad);
 
     u32x4 a = {0, 0, 0, 0};
+    // boundary row: zero padding, AAD, partial blocks or the length block
+    auto boundary_row = [&](int64_t v0) {
+        const int64_t v = v0 + lane;
+        const uint64_t j = (uint64_t)(v - na);
+        const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
+        u32x4 X = {0, 0, 0, 0};
+        if (GH && v >= 0 && v < na) {
+            X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
+        } else if (v >= na && v < na + ndat) {
+            const u32x4 x = load_block_partial(in, j, d.len);
+            const u32x4 o = x ^ ks;
+            store_block_partial(out, j, d.len, o);
+            X = enc ? mask_block(o, j, d.len) : x;
+        } else if (GH && v == na + ndat) {
+            const uint64_t abits = d.aad_len * 8, cbits = d.len * 8;
+            X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
+                      bswap32((uint32_t)cbits)};
+        }
+        if (GH)
+            a = ghash_mul8(a, X, lds, gk);
+    };
+
+    uint32_t r = r0;
+    if (GH && AADROWS) {
+        // Rows of whole AAD blocks, [ra0, ra1), take the GHASH step only.  They
+        // follow at most one boundary row (zero prefix and AAD start) and
+        // precede every data row, so they are peeled off before the main loop.
+        const int64_t vb = vbase;
+        const int64_t rz = vb >= 0 ? 0 : (-vb + 63) >> 6;        // first row with v0 >= 0
+        const int64_t fit = nafull - vb;                          // rows r with v0 + 64 <= nafull: r < fit / 64
+        int64_t ra0 = rz > (int64_t)r0 ? rz : (int64_t)r0;
+        int64_t ra1 = fit >= 64 ? fit >> 6 : 0;
+        ra1 = ra1 < (int64_t)R ? ra1 : (int64_t)R;
+        if (ra1 > ra0) {
+            for (; (int64_t)r < ra0; ++r)
+                boundary_row(vb + 64 * (int64_t)r);
+            for (; (int64_t)r < ra1; ++r)
+                a = ghash_mul8(a, aad_g[(uint64_t)(vb + 64 * (int64_t)r) + (uint64_t)lane], lds, gk);
+        }
+    }
+
     uint32_t hc = 0xffffffffu;  // upper counter bits `cur` belongs to (none yet)
     Ctr2 cur = {0, 0, 0, 0};
-    for (uint32_t r = r0; r < R; ++r) {
+    for (; r < R; ++r) {
         // re-read the round keys with scalar loads each row instead of holding
         // 4*(Nr+1) of them (or their lane-rotated copies) in registers
         rk = rk_base;
@@ -899,29 +942,8 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             __builtin_nontemporal_store(o, out_g + j);
             if (GH)
                 a = ghash_mul8(a, enc ? o : x, lds, gk);
-        } else if (GH && v0 >= 0 && v0 + 64 <= nafull) {
-            // all 64 lanes hold whole AAD blocks: GHASH only
-            a = ghash_mul8(a, aad_g[(uint64_t)v0 + (uint64_t)lane], lds, gk);
         } else {
-            // boundary row: zero padding, AAD, partial blocks or the length block
-            const int64_t v = v0 + lane;
-            const uint64_t j = (uint64_t)(v - na);
-            const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
-            u32x4 X = {0, 0, 0, 0};
-            if (GH && v >= 0 && v < na) {
-                X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
-            } else if (v >= na && v < na + ndat) {
-                const u32x4 x = load_block_partial(in, j, d.len);
-                const u32x4 o = x ^ ks;
-                store_block_partial(out, j, d.len, o);
-                X = enc ? mask_block(o, j, d.len) : x;
-            } else if (GH && v == na + ndat) {
-                const uint64_t abits = d.aad_len * 8, cbits = d.len * 8;
-                X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
-                          bswap32((uint32_t)cbits)};
-            }
-            if (GH)
-                a = ghash_mul8(a, X, lds, gk);
+            boundary_row(v0);
         }
     }
     if (!GH)
@@ -947,12 +969,21 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         partials[d.tile_base + t] = a;
 }
 
-template <int WAVES, bool BATCH, bool GH>
+// Kernel variants: GCM; counter mode only; GCM with the GHASH-only pass over
+// whole AAD rows (a kernel of its own so that its extra loop leaves the
+// register allocation of the others alone), used for single messages whose
+// AAD spans at least 64 rows of blocks.
+constexpr int kModeGcm = 0, kModeCtr = 1, kModeGcmAad = 2;
+constexpr uint64_t kAadRowsMinBytes = 64 * 64 * 16;
+
+template <int WAVES, bool BATCH, int MODE>
 __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restrict__ descs,
                                                           const WorkItem *__restrict__ items, uint32_t n_items,
                                                           MsgDesc single, const uint32_t *__restrict__ te0g,
                                                           u32x4 *__restrict__ partials, uint32_t *counters)
 {
+    constexpr bool GH = MODE != kModeCtr;
+    constexpr bool AADROWS = MODE == kModeGcmAad;
     __shared__ u32x4 lds_v[8192];  // 128 KiB: GHASH table, then the replicated T-tables
     const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
 
@@ -1024,11 +1055,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.tile_hi) {
             if (d.nr == 10)
-                wave_tile<10, GH>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<10, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
             else if (d.nr == 12)
-                wave_tile<12, GH>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<12, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile<14, GH>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<14, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
         }
     }
 }
@@ -1221,14 +1252,17 @@ static hipError_t launch_tiles_w(const MsgDesc *descs, const WorkItem *items, ui
                                  hipStream_t s)
 {
     if (descs)
-        hipLaunchKernelGGL((k_gcm_tiles<WAVES, true, true>), dim3(grid), dim3(WAVES * 64), 0, s, descs, items,
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, true, kModeGcm>), dim3(grid), dim3(WAVES * 64), 0, s, descs, items,
                            n_items, MsgDesc{}, te0, partials, counters);
     else if (single->op == 2)
-        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, false>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
-                           n_items, *single, te0, partials, counters);
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeCtr>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
+                           nullptr, n_items, *single, te0, partials, counters);
+    else if (single->aad_len >= kAadRowsMinBytes)
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeGcmAad>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
+                           nullptr, n_items, *single, te0, partials, counters);
     else
-        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, true>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr, nullptr,
-                           n_items, *single, te0, partials, counters);
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeGcm>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
+                           nullptr, n_items, *single, te0, partials, counters);
     return hipGetLastError();
 }
 
@@ -1255,13 +1289,13 @@ int max_groups_per_cu(int waves)
     hipError_t e = hipErrorInvalidValue;
     switch (waves) {
     case 8:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false, true>, 8 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<8, false, kModeGcm>, 8 * 64, 0);
         break;
     case 12:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<12, false, true>, 12 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<12, false, kModeGcm>, 12 * 64, 0);
         break;
     case 16:
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false, true>, 16 * 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_gcm_tiles<16, false, kModeGcm>, 16 * 64, 0);
         break;
     }
     return (e == hipSuccess && n > 0) ? n : 1;

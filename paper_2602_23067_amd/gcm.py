@@ -327,8 +327,9 @@ class Context:
 
     def encrypt_async(self, slot: int, iv: bytes, aad, pt, ct, tag_d, workspace, stream=None) -> None:
         _check(load().gcm_encrypt_async(self._h, slot, _host(iv), len(iv), _dev(aad),
-                                        0 if aad is None else aad.numel(), _dev(pt), pt.numel(), _dev(ct),
-                                        _dev(tag_d), _dev(workspace), workspace.numel(), _stream(stream)))
+                                        0 if aad is None else aad.numel(), _dev(pt),
+                                        0 if pt is None else pt.numel(), _dev(ct), _dev(tag_d), _dev(workspace),
+                                        workspace.numel(), _stream(stream)))
 
     def decrypt_verify_async(self, slot: int, iv: bytes, aad, ct, tag_d, pt, accept_d, workspace,
                              stream=None) -> None:
