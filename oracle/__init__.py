@@ -58,6 +58,11 @@ def lib() -> ctypes.CDLL:
         L.oracle_gcm_decrypt_verify.argtypes = [u8p, sz, u8p, sz, u8p, u64, u8p, u64, u8p, u8p,
                                                 ctypes.POINTER(ctypes.c_int)]
         L.oracle_gcm_decrypt_verify.restype = ctypes.c_int
+        L.oracle_gcm_decrypt_verify_t.argtypes = [u8p, sz, u8p, sz, u8p, u64, u8p, u64, u8p, sz, u8p,
+                                                  ctypes.POINTER(ctypes.c_int)]
+        L.oracle_gcm_decrypt_verify_t.restype = ctypes.c_int
+        L.oracle_gcm_j0.argtypes = [u8p, sz, u8p, sz, u8p]
+        L.oracle_gcm_j0.restype = ctypes.c_int
         L.oracle_gf8_mul.argtypes = [ctypes.c_uint8, ctypes.c_uint8]
         L.oracle_gf8_mul.restype = ctypes.c_uint8
         L.oracle_gf8_inv.argtypes = [ctypes.c_uint8]
@@ -245,6 +250,28 @@ def gcm_decrypt_verify(key: bytes, iv: bytes, aad, ct, tag: bytes, out: Optional
     if rc:
         raise OracleError(rc)
     return pt, bool(acc.value)
+
+
+def gcm_decrypt_verify_t(key: bytes, iv: bytes, aad, ct, tag: bytes, out: Optional[np.ndarray] = None):
+    """GCM-AD with a truncated tag (len(tag) bytes): (plaintext or zeros, accept)."""
+    a = _buf(aad)
+    c = _buf(ct)
+    pt = out if out is not None else np.empty(c.size, dtype=np.uint8)
+    acc = ctypes.c_int(-1)
+    t = bytes(tag)
+    rc = lib().oracle_gcm_decrypt_verify_t(bytes(key), len(key), bytes(iv), len(iv), _ptr(a), a.size,
+                                           _ptr(c), c.size, t, len(t), _ptr(pt), ctypes.byref(acc))
+    if rc:
+        raise OracleError(rc)
+    return pt, bool(acc.value)
+
+
+def gcm_j0(key: bytes, iv: bytes) -> bytes:
+    out = ctypes.create_string_buffer(16)
+    rc = lib().oracle_gcm_j0(bytes(key), len(key), bytes(iv), len(iv), out)
+    if rc:
+        raise OracleError(rc)
+    return out.raw
 
 
 def gcm_status(key: bytes, iv: bytes, aad_len: int, length: int) -> int:

@@ -16,14 +16,19 @@
  *   GF(2^128)  -- SP 800-38D sec. 6.3, bit-serial product (Algorithm 1).
  *   GHASH      -- SP 800-38D sec. 6.4, sequential Horner: Y_i = (Y_{i-1}^X_i)*H.
  *   GCTR       -- SP 800-38D sec. 6.5 with inc32 (sec. 6.2).
- *   GCM-AE/AD  -- SP 800-38D sec. 7.1 / 7.2, 96-bit IV, 128-bit tag.
+ *   GCM-AE/AD  -- SP 800-38D sec. 7.1 / 7.2: any IV length (J0 = IV||0^31||1
+ *                 for 96 bits, else GHASH of the padded IV and its length,
+ *                 sec. 7.1 step 2); tags of t = 128, 120, 112, 104, 96, 64
+ *                 or 32 bits (sec. 5.2.1.2), T = MSB_t of the full tag.
  *
  * Readings where the paper is silent (listed in full in the design notes):
  *   - key sizes 16/24/32 bytes accepted (the paper uses AES-128 only);
- *   - IV must be 12 bytes (the paper's 96-bit nonces); tag is 16 bytes;
+ *   - IVs are whole bytes, 1 .. 2^61 - 1 of them (the paper uses 96-bit
+ *     nonces; SP 800-38D allows any length from 1 bit); tags are 16 bytes
+ *     unless a truncated length is given;
  *   - on a tag mismatch the plaintext output is zero-filled (the paper's
  *     payload-suppression behaviour) and *accept is 0;
- *   - tags are compared over all 16 bytes without early exit.
+ *   - tags are compared over all t bytes without early exit.
  *
  * Parity pins (all in tests/test_oracle_*.py): exhaustive GF(2^8) inverse,
  * S-box invariants, single-block equality with OpenSSL's AES-ECB, the
@@ -375,6 +380,8 @@ enum {
 #define ORACLE_MAX_LEN ((((uint64_t)1) << 36) - 32)
 /* |A| <= 2^64 - 1 bits  =>  aad_len < 2^61 bytes */
 #define ORACLE_MAX_AAD ((((uint64_t)1) << 61) - 1)
+/* 1 <= len(IV) <= 2^64 - 1 bits, in whole bytes */
+#define ORACLE_MAX_IV ((((uint64_t)1) << 61) - 1)
 
 static void put_be64(uint8_t *p, uint64_t v)
 {
@@ -404,17 +411,27 @@ static int gcm_setup(const uint8_t *key, size_t key_len, const uint8_t *iv, size
     *nr = key_expansion(key, key_len, w);
     if (*nr == 0)
         return ORACLE_E_KEYLEN;
-    if (iv_len != 12)
+    if (iv_len == 0 || iv_len > ORACLE_MAX_IV)
         return ORACLE_E_IVLEN;
     if (len > ORACLE_MAX_LEN || aad_len > ORACLE_MAX_AAD)
         return ORACLE_E_TOOLONG;
     uint8_t zero[16] = {0};
     aes_cipher(w, *nr, zero, h); /* H = CIPH_K(0^128) */
-    memcpy(j0, iv, 12);          /* J0 = IV || 0^31 || 1 */
-    j0[12] = 0;
-    j0[13] = 0;
-    j0[14] = 0;
-    j0[15] = 1;
+    if (iv_len == 12) {
+        memcpy(j0, iv, 12); /* J0 = IV || 0^31 || 1 */
+        j0[12] = 0;
+        j0[13] = 0;
+        j0[14] = 0;
+        j0[15] = 1;
+    } else {
+        /* J0 = GHASH_H(IV || 0^(s+64) || [len(IV)]_64), s pads IV to whole blocks */
+        uint8_t y[16] = {0}, lb[16];
+        ghash_absorb_padded(y, h, iv, iv_len);
+        put_be64(lb, 0);
+        put_be64(lb + 8, (uint64_t)iv_len * 8);
+        ghash_absorb_block(y, h, lb);
+        memcpy(j0, y, 16);
+    }
     return ORACLE_OK;
 }
 
@@ -440,22 +457,26 @@ int oracle_gcm_encrypt(const uint8_t *key, size_t key_len, const uint8_t *iv, si
     return ORACLE_OK;
 }
 
-int oracle_gcm_decrypt_verify(const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
-                              const uint8_t *aad, uint64_t aad_len, const uint8_t *ct, uint64_t len,
-                              const uint8_t tag[16], uint8_t *pt, int *accept)
+/* tag lengths of sec. 5.2.1.2, in bytes */
+static int valid_tag_len(size_t t) { return t == 16 || t == 15 || t == 14 || t == 13 || t == 12 || t == 8 || t == 4; }
+
+/* GCM-AD with a tag of tag_len bytes: accept iff T equals MSB_t(GCTR_K(J0, S)) */
+int oracle_gcm_decrypt_verify_t(const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                                const uint8_t *aad, uint64_t aad_len, const uint8_t *ct, uint64_t len,
+                                const uint8_t *tag, size_t tag_len, uint8_t *pt, int *accept)
 {
     uint8_t w[AES_MAX_WORDS][4], h[16], j0[16];
     int nr;
     int rc = gcm_setup(key, key_len, iv, iv_len, aad_len, len, w, &nr, h, j0);
     if (rc)
         return rc;
-    if ((len && (!pt || !ct)) || (aad_len && !aad) || !tag || !accept)
+    if ((len && (!pt || !ct)) || (aad_len && !aad) || !tag || !accept || !valid_tag_len(tag_len))
         return ORACLE_E_ARG;
     uint8_t s[16], ekj0[16];
     gcm_hash(h, aad, aad_len, ct, len, s);
     aes_cipher(w, nr, j0, ekj0);
     uint8_t diff = 0;
-    for (int k = 0; k < 16; k++)
+    for (size_t k = 0; k < tag_len; k++)
         diff |= (uint8_t)((ekj0[k] ^ s[k]) ^ tag[k]);
     if (diff == 0) {
         uint8_t icb[16];
@@ -469,6 +490,21 @@ int oracle_gcm_decrypt_verify(const uint8_t *key, size_t key_len, const uint8_t 
         *accept = 0;
     }
     return ORACLE_OK;
+}
+
+int oracle_gcm_decrypt_verify(const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                              const uint8_t *aad, uint64_t aad_len, const uint8_t *ct, uint64_t len,
+                              const uint8_t tag[16], uint8_t *pt, int *accept)
+{
+    return oracle_gcm_decrypt_verify_t(key, key_len, iv, iv_len, aad, aad_len, ct, len, tag, 16, pt, accept);
+}
+
+/* J0 for an IV (sec. 7.1 step 2), exposed for the pins */
+int oracle_gcm_j0(const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len, uint8_t out[16])
+{
+    uint8_t w[AES_MAX_WORDS][4], h[16];
+    int nr;
+    return gcm_setup(key, key_len, iv, iv_len, 0, 0, w, &nr, h, out);
 }
 
 /* ------------------------------------------------------------------ */

@@ -98,7 +98,8 @@ def gcm_encrypt(key: bytes, iv: bytes, aad: bytes, pt: bytes):
 
 
 def gcm_decrypt(key: bytes, iv: bytes, aad: bytes, ct: bytes, tag: bytes):
-    """Returns (plaintext, accepted)."""
+    """Returns (plaintext, accepted); a tag shorter than 16 bytes is checked
+    as a truncated tag of that length."""
     L = _load()
     ctx = L.EVP_CIPHER_CTX_new()
     try:
@@ -111,8 +112,8 @@ def gcm_decrypt(key: bytes, iv: bytes, aad: bytes, ct: bytes, tag: bytes):
         out = ctypes.create_string_buffer(len(ct) + 16)
         for off, chunk in _chunks(ct):
             assert L.EVP_DecryptUpdate(ctx, ctypes.byref(out, off), ctypes.byref(n), chunk, len(chunk)) == 1
-        tbuf = ctypes.create_string_buffer(bytes(tag), 16)
-        assert L.EVP_CIPHER_CTX_ctrl(ctx, _EVP_CTRL_GCM_SET_TAG, 16, tbuf) == 1
+        tbuf = ctypes.create_string_buffer(bytes(tag), len(tag))
+        assert L.EVP_CIPHER_CTX_ctrl(ctx, _EVP_CTRL_GCM_SET_TAG, len(tag), tbuf) == 1
         ok = L.EVP_DecryptFinal_ex(ctx, None, ctypes.byref(n)) == 1
         return out.raw[: len(ct)], ok
     finally:

@@ -340,10 +340,68 @@ def test_gcm_every_single_bit_flip_rejected_and_zero_filled():
     assert not ok
 
 
+@pytest.mark.parametrize("iv_len", [1, 2, 7, 8, 11, 13, 15, 16, 17, 31, 32, 33, 60, 64, 100, 127, 128])
+def test_gcm_other_iv_lengths_match_openssl(iv_len):
+    """SP 800-38D sec. 7.1 step 2: J0 = GHASH_H(IV || 0^(s+64) || [len(IV)]_64) for IVs other than 96 bits.
+    OpenSSL accepts IVs of up to 128 bytes (eight GHASH blocks); longer IVs take the same oracle code
+    over more blocks."""
+    rng = random.Random(360 + iv_len)
+    for plen, alen in ((0, 0), (1, 0), (37, 13), (1000, 80), (4097, 2880)):
+        key = rng.randbytes(rng.choice([16, 24, 32]))
+        iv, aad, pt = rng.randbytes(iv_len), rng.randbytes(alen), rng.randbytes(plen)
+        ct, tag = oracle.gcm_encrypt(key, iv, aad, pt)
+        rct, rtag = ref.gcm_encrypt(key, iv, aad, pt)
+        assert ct.tobytes() == rct and tag == rtag, (iv_len, plen, alen)
+        back, ok = oracle.gcm_decrypt_verify(key, iv, aad, ct, tag)
+        assert ok and back.tobytes() == pt
+
+
+def test_gcm_j0_against_openssl_block_cipher():
+    """J0 pinned without the oracle's GHASH: with P and A empty the tag is
+    E_K(J0) (S = GHASH of the all-zero length block = 0), so OpenSSL's GCM tag
+    must equal OpenSSL's AES-ECB of the oracle's J0."""
+    rng = random.Random(370)
+    for iv_len in (1, 8, 12, 16, 20, 60, 128):
+        key, iv = rng.randbytes(16), rng.randbytes(iv_len)
+        j0 = oracle.gcm_j0(key, iv)
+        if iv_len == 12:
+            assert j0 == iv + b"\x00\x00\x00\x01"
+        _, rtag = ref.gcm_encrypt(key, iv, b"", b"")
+        assert ref.aes_ecb_encrypt(key, j0) == rtag, iv_len
+
+
+@pytest.mark.parametrize("tag_len", [4, 8, 12, 13, 14, 15, 16])
+def test_gcm_truncated_tags(tag_len):
+    """SP 800-38D sec. 5.2.1.2 / 7.2: T = MSB_t(full tag); verification compares t bits."""
+    rng = random.Random(380 + tag_len)
+    key, iv, aad, pt = _rand_case(rng, 32, 45, 11)
+    ct, tag = oracle.gcm_encrypt(key, iv, aad, pt)
+    t = tag[:tag_len]
+    back, ok = oracle.gcm_decrypt_verify_t(key, iv, aad, ct, t)
+    assert ok and back.tobytes() == pt
+    assert ref.gcm_decrypt(key, iv, aad, ct.tobytes(), t) == (pt, True)
+    for pos in range(tag_len * 8):
+        bad = bytearray(t)
+        bad[pos // 8] ^= 1 << (pos % 8)
+        out, ok = oracle.gcm_decrypt_verify_t(key, iv, aad, ct, bytes(bad))
+        assert not ok and not out.any()
+        assert not ref.gcm_decrypt(key, iv, aad, ct.tobytes(), bytes(bad))[1]
+
+
+def test_gcm_truncated_tag_lengths_outside_the_standard_rejected():
+    key, iv = bytes(16), bytes(12)
+    ct, tag = oracle.gcm_encrypt(key, iv, b"", b"abc")
+    for bad_len in (0, 1, 3, 5, 7, 9, 11):
+        with pytest.raises(oracle.OracleError) as e:
+            oracle.gcm_decrypt_verify_t(key, iv, b"", ct, tag[:bad_len])
+        assert e.value.code == oracle.E_ARG
+
+
 def test_gcm_argument_errors():
     assert oracle.gcm_status(bytes(20), bytes(12), 0, 0) == oracle.E_KEYLEN
-    assert oracle.gcm_status(bytes(16), bytes(8), 0, 0) == oracle.E_IVLEN
-    assert oracle.gcm_status(bytes(16), bytes(16), 0, 0) == oracle.E_IVLEN
+    assert oracle.gcm_status(bytes(16), b"", 0, 0) == oracle.E_IVLEN
+    assert oracle.gcm_status(bytes(16), bytes(8), 0, 0) == oracle.OK
+    assert oracle.gcm_status(bytes(16), bytes(16), 0, 0) == oracle.OK
     assert oracle.gcm_status(bytes(16), bytes(12), 0, (1 << 36) - 31) == oracle.E_TOOLONG
     assert oracle.gcm_status(bytes(16), bytes(12), 1 << 61, 0) == oracle.E_TOOLONG
 
