@@ -500,8 +500,8 @@ def main():
     log2B = args.log2_tile
     if not log2B:
         # the library chooses the tile size; recover it from the workspace size (a 256-byte counter
-        # block, 16 bytes per tile partial, one 16-byte slot for E_K(J0))
-        tiles = (ctx.workspace_size(n, aad_len) - 256) // 16 - 1
+        # block, 16 bytes per tile partial, 16-byte slots for E_K(J0) and J0)
+        tiles = (ctx.workspace_size(n, aad_len) - 256) // 16 - 2
     else:
         tiles = -(-blocks // (1 << log2B))
     tile_bytes = 2 * n + aad_len + 16 * tiles

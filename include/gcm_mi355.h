@@ -23,9 +23,14 @@
  *  - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued on
  *    it in stream order.
  *  - Keys are 16, 24 or 32 bytes (AES-128/192/256).  IVs are 12 bytes (the
- *    paper's 96-bit nonces); J0 = IV || 0^31 || 1 and data block i (0-based)
- *    uses counter inc32^(i+1)(J0), independent of launch geometry (the
- *    paper's geometry-agnostic counter mapping).  Tags are 16 bytes.
+ *    paper's 96-bit nonces, J0 = IV || 0^31 || 1) or, on the single-message
+ *    GCM calls (one-shot, asynchronous, host pipeline), any length from 1 to
+ *    1024 bytes (SP 800-38D sec. 7.1 step 2: J0 = GHASH_H(IV || 0-pad ||
+ *    0^64 || [len(IV)]_64), computed on the device); batches, the serving
+ *    loop and the counter-mode-only calls take 12-byte IVs.  Data block i
+ *    (0-based) uses counter inc32^(i+1)(J0), independent of launch geometry
+ *    (the paper's geometry-agnostic counter mapping).  Tags are 16 bytes
+ *    except on the _ex calls (truncated tags).
  *  - Limits (SP 800-38D): len <= 2^36 - 32 bytes, aad_len < 2^61 bytes,
  *    else GCM_E_TOOLONG.
  *  - in == out is allowed (in place); partially overlapping in/out is
@@ -47,7 +52,7 @@ extern "C" {
 #define GCM_OK 0
 #define GCM_E_ARG (-1)     /* null pointer, bad size, bad op, misaligned pointer */
 #define GCM_E_KEYLEN (-2)  /* key length not 16, 24 or 32 */
-#define GCM_E_IVLEN (-3)   /* IV length not 12 */
+#define GCM_E_IVLEN (-3)   /* IV length not allowed by the call (see the conventions above) */
 #define GCM_E_TOOLONG (-4) /* len or aad_len beyond the SP 800-38D limits */
 #define GCM_E_NOMEM (-5)   /* device or pinned allocation failed / budget exceeded */
 #define GCM_E_HIP (-6)     /* a HIP runtime call failed */
@@ -113,11 +118,25 @@ int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const u
                        const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
                        const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream);
 
+/* gcm_encrypt / gcm_decrypt_verify with a truncated tag of tag_len bytes
+ * (SP 800-38D sec. 5.2.1.2: t = 128, 120, 112, 104, 96, or, for the uses
+ * its Appendix C allows, 64 or 32 bits; tag_len 16, 15, 14, 13, 12, 8 or 4,
+ * else GCM_E_ARG).  Encrypt writes T = MSB_t(full tag) to tag_out (tag_len
+ * bytes, host); decrypt-verify compares tag_len bytes (host) without early
+ * exit. */
+int gcm_encrypt_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                   const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
+                   uint8_t *tag_out, size_t tag_len, void *stream);
+int gcm_decrypt_verify_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                          const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                          const uint8_t *tag, size_t tag_len, uint8_t *pt_d, int *accept, void *stream);
+
 /* ---------------------------------------------------------------- asynchronous, resident key */
 
 /* Device scratch bytes an asynchronous call on a message of `len` data bytes
  * and `aad_len` AAD bytes needs (the per-tile partial hashes of the map
- * phase and the block E_K(J0) that the reduce phase adds).  A workspace may be
+ * phase, the block E_K(J0) that the reduce phase adds, and J0 itself for IVs
+ * other than 96 bits).  A workspace may be
  * reused by calls that are ordered on one stream. */
 uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
 

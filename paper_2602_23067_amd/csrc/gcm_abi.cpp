@@ -40,6 +40,9 @@ int gcm::fail_hip(hipError_t e, const char *what)
 
 extern "C" const char *gcm_last_error(void) { return g_last_error.c_str(); }
 
+// placeholder IV for fill_desc when set_iv fills the descriptor's IV afterwards
+static const uint8_t kZeroIv[12] = {0};
+
 // ---------------------------------------------------------------- context
 
 static uint32_t ceil_log2(uint64_t x)
@@ -356,6 +359,35 @@ void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, ui
     d->nr = nr;
     d->groups = (uint32_t)((d->n_tiles + waves - 1) / waves);
     d->fix_lane = 1;  // callers that mix many keys switch large-table fix-ups off per message
+    d->j0 = 0;
+    d->tag_len = 16;
+}
+
+bool gcm::valid_iv_len(size_t n) { return n >= 1 && n <= (size_t)kMaxIvBytes; }
+
+int gcm::set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStream_t s)
+{
+    if (iv_len == 12) {
+        for (int i = 0; i < 3; ++i)
+            d->iv[i] = (uint32_t)iv[4 * i] | ((uint32_t)iv[4 * i + 1] << 8) | ((uint32_t)iv[4 * i + 2] << 16) |
+                       ((uint32_t)iv[4 * i + 3] << 24);
+        d->j0 = 0;
+        return GCM_OK;
+    }
+    if (!valid_iv_len(iv_len))
+        return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
+    IvArg a;
+    std::memset(&a, 0, sizeof a);
+    a.len = (uint32_t)iv_len;
+    std::memcpy(a.b, iv, iv_len);
+    // per message: its T tile partials, E_K(J0), then J0
+    uint8_t *j0 = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1) + 16 * (d->tile_base + d->n_tiles + 1);
+    hipError_t e = launch_j0(a, d->slot, j0, s);
+    if (e != hipSuccess)
+        return fail_hip(e, "J0 kernel launch");
+    d->iv[0] = d->iv[1] = d->iv[2] = 0;
+    d->j0 = (uint64_t)j0;
+    return GCM_OK;
 }
 
 int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
@@ -375,11 +407,11 @@ int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const 
 
 uint64_t gcm::workspace_counter_bytes(uint64_t n_msgs) { return ((4 + 4 * n_msgs) + 255) / 256 * 256; }
 
-// counters, then per message its tile partials followed by one 16-byte slot
-// for E_K(J0)
+// counters, then per message its tile partials followed by two 16-byte slots:
+// E_K(J0), and J0 when the IV is not 96 bits
 uint64_t gcm::workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs)
 {
-    return workspace_counter_bytes(n_msgs) + 16 * (total_tiles + n_msgs);
+    return workspace_counter_bytes(n_msgs) + 16 * (total_tiles + 2 * n_msgs);
 }
 
 // Enqueue the tile kernel for tiles [d.tile_lo, d.tile_hi) of one message on `s`.
@@ -463,8 +495,8 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
 {
     if (!ctx || !iv || !tag_d || (op == 1 && !ok_d) || !ws)
         return fail(GCM_E_ARG, "NULL argument");
-    if (iv_len != 12)
-        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    if (!valid_iv_len(iv_len))
+        return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
     int rc = check_message(aad_len, len, aad_d, in_d, out_d);
     if (rc)
         return rc;
@@ -477,7 +509,7 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
     launch_shape(ctx, m, &log2B, &waves, &gpc);
     MsgDesc d;
-    fill_desc(&d, op, iv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
+    fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
               (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), 0, log2B, waves, 0);
     d.nr = ctx->slot_nr[slot];
     if (ws_bytes < workspace_bytes_for(d.n_tiles, 1))
@@ -486,7 +518,11 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return fail_hip(e, "hipSetDevice");
-    return launch_single(ctx, d, waves, gpc, ws, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    rc = set_iv(&d, iv, iv_len, ws, s);
+    if (rc)
+        return rc;
+    return launch_single(ctx, d, waves, gpc, ws, s);
 }
 
 extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
@@ -508,16 +544,20 @@ extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8
 
 // ---------------------------------------------------------------- one-shot entry points
 
+static bool valid_tag_len(size_t t) { return t == 16 || t == 15 || t == 14 || t == 13 || t == 12 || t == 8 || t == 4; }
+
 static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                    const uint8_t *aad_d, uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d,
-                   const uint8_t *tag_in, uint8_t *tag_out, int *accept, void *stream)
+                   const uint8_t *tag_in, uint8_t *tag_out, int *accept, void *stream, size_t tag_len = 16)
 {
     if (!ctx || !key || !iv || (op == 0 && !tag_out) || (op == 1 && (!tag_in || !accept)))
         return fail(GCM_E_ARG, "NULL argument");
     if (!valid_key_len(key_len))
         return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
-    if (iv_len != 12)
-        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    if (!valid_iv_len(iv_len))
+        return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
+    if (!valid_tag_len(tag_len))
+        return fail(GCM_E_ARG, "tag length %zu is not 16, 15, 14, 13, 12, 8 or 4", tag_len);
     int rc = check_message(aad_len, len, aad_d, in_d, out_d);
     if (rc)
         return rc;
@@ -540,13 +580,17 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     uint8_t *d_tag = ctx->d_io;                                 // 16 bytes
     int32_t *d_ok = reinterpret_cast<int32_t *>(ctx->d_io + 16);  // 4 bytes
     if (op == 1) {
-        e = hipMemcpyAsync(d_tag, tag_in, 16, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(d_tag, tag_in, tag_len, hipMemcpyHostToDevice, s);
         if (e != hipSuccess)
             return fail_hip(e, "tag upload");
     }
     MsgDesc d;
-    fill_desc(&d, op, iv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)d_tag,
+    fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)d_tag,
               (uint64_t)d_ok, (uint64_t)(ctx->d_slots + kSlotBytes * slot), slot_nr(key_len), log2B, waves, 0);
+    d.tag_len = (uint32_t)tag_len;
+    rc = set_iv(&d, iv, iv_len, ctx->d_ws, s);
+    if (rc)
+        return rc;
     rc = launch_single(ctx, d, waves, gpc, ctx->d_ws, s);
     if (rc)
         return rc;
@@ -556,13 +600,30 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     if (e != hipSuccess)
         return fail_hip(e, "result download");
     if (op == 0) {
-        std::memcpy(tag_out, ctx->h_io, 16);
+        std::memcpy(tag_out, ctx->h_io, tag_len);
     } else {
         int32_t ok;
         std::memcpy(&ok, ctx->h_io + 16, 4);
         *accept = ok == 1 ? 1 : 0;
     }
     return GCM_OK;
+}
+
+extern "C" int gcm_encrypt_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
+                              const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
+                              uint8_t *tag_out, size_t tag_len, void *stream)
+{
+    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
+                   stream, tag_len);
+}
+
+extern "C" int gcm_decrypt_verify_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv,
+                                     size_t iv_len, const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d,
+                                     uint64_t len, const uint8_t *tag, size_t tag_len, uint8_t *pt_d, int *accept,
+                                     void *stream)
+{
+    return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream,
+                   tag_len);
 }
 
 extern "C" int gcm_encrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,

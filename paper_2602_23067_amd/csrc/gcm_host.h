@@ -81,6 +81,12 @@ void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_
 int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
 uint64_t workspace_counter_bytes(uint64_t n_msgs);
 uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
+// IV lengths the device path takes (1..kMaxIvBytes bytes)
+bool valid_iv_len(size_t n);
+// Set the descriptor's IV: 12 bytes go in d.iv; any other length enqueues the
+// J0 kernel on `s` (d.slot must be set), writing J0 to the message's J0 slot
+// of workspace `ws` (after its partials and E_K(J0)), and points d.j0 there.
+int set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStream_t s);
 int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
 // release the host pipeline's streams, events and buffers (gcm_ctx_destroy)
 void pipeline_release(gcm_ctx *ctx);
@@ -105,6 +111,7 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
 int max_groups_per_cu(int waves);
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
                           uint32_t *counters, hipStream_t s);
+hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, hipStream_t s);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);
 

@@ -69,6 +69,18 @@ struct MsgDesc {
     uint32_t nr;         // AES rounds
     uint32_t groups;     // workgroup items for this message
     uint32_t fix_lane;   // 1: per-lane fix-up tables H^(63-l); 0: exponent bits over H^(2^k)
+    uint64_t j0;         // device address of J0 (16 bytes) for IVs other than 96 bits; 0: J0 = IV || 0^31 || 1
+    uint32_t tag_len;    // tag bytes written (encrypt) or compared (decrypt): 16, or 15, 14, 13, 12, 8, 4
+    uint32_t pad1;
+};
+
+// IVs other than 96 bits: J0 = GHASH_H(IV || 0-pad || 0^64 || [len(IV)]_64),
+// computed on the device from IV bytes passed by value
+constexpr int kMaxIvBytes = 1024;
+struct IvArg {
+    uint32_t len;
+    uint32_t pad[3];
+    uint8_t b[kMaxIvBytes];
 };
 
 // One unit of work for a workgroup: `waves` consecutive wave tiles of one message.

@@ -822,10 +822,12 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
 // p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
 // across the wave.  With GH false the tile is counter mode only (no GHASH,
-// no partial).  AADROWS adds a GHASH-only pass over rows of whole AAD blocks
-// (it costs the main loop its batching of LDS reads, so it is only compiled
-// into a kernel variant of its own).
-template <int NR, bool GH, bool AADROWS>
+// no partial).  AADROWS adds a GHASH-only pass over rows of whole AAD blocks,
+// J0DEV reads J0 from device memory (IVs other than 96 bits) instead of
+// forming IV || 0^31 || 1; both cost the main loop its batching of LDS reads
+// (a run-time counter base, or the extra loop, leaves it fewer registers), so
+// each is compiled only into kernel variants of its own.
+template <int NR, bool GH, bool AADROWS, bool J0DEV>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
                           const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
 {
@@ -833,9 +835,19 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     const CONST_AS uint32_t *te = cptr<uint32_t>(te0g);
     const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
     const CONST_AS uint32_t *rk = rk_base;
+    // J0 = IV || 0^31 || 1, or a J0 computed from a longer or shorter IV;
+    // data block j uses counter value c1 + j, E_K(J0) counter value c1 - 1
+    uint32_t iv0 = d.iv[0], iv1 = d.iv[1], iv2 = d.iv[2], c1 = 2u;
+    if (J0DEV) {
+        const CONST_AS uint32_t *jw = cptr<uint32_t>(reinterpret_cast<const void *>(d.j0));
+        iv0 = jw[0];
+        iv1 = jw[1];
+        iv2 = jw[2];
+        c1 = bswap32(jw[3]) + 1u;
+    }
     AesCtx c;
     {
-        const uint32_t s0 = d.iv[0] ^ rk[0], s1 = d.iv[1] ^ rk[1], s2 = d.iv[2] ^ rk[2];
+        const uint32_t s0 = iv0 ^ rk[0], s1 = iv1 ^ rk[1], s2 = iv2 ^ rk[2];
         c.u0 = uniform(te_u(lds, 0, B0(s0)) ^ te_u(lds, 1, B1(s1)) ^ te_u(lds, 2, B2(s2)) ^ rk[4]);
         c.u1 = uniform(te_u(lds, 0, B0(s1)) ^ te_u(lds, 1, B1(s2)) ^ te_u(lds, 3, B3(s0)) ^ rk[5]);
         c.u2 = uniform(te_u(lds, 0, B0(s2)) ^ te_u(lds, 2, B2(s0)) ^ te_u(lds, 3, B3(s1)) ^ rk[6]);
@@ -846,7 +858,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     if (GH && t == 0) {
         // E_K(J0) is the keystream block of counter value 1; the wave that owns
         // tile 0 leaves it after the message's partials for the combine
-        const u32x4 ek = aes_ctr<NR>(1u, c, rk, lds, lk);
+        const u32x4 ek = aes_ctr<NR>(c1 - 1u, c, rk, lds, lk);
         if (lane == 0)
             partials[d.tile_base + d.n_tiles] = ek;
     }
@@ -871,7 +883,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     auto boundary_row = [&](int64_t v0) {
         const int64_t v = v0 + lane;
         const uint64_t j = (uint64_t)(v - na);
-        const u32x4 ks = aes_ctr<NR>((uint32_t)j + 2u, c, rk, lds, lk);
+        const u32x4 ks = aes_ctr<NR>((uint32_t)j + c1, c, rk, lds, lk);
         u32x4 X = {0, 0, 0, 0};
         if (GH && v >= 0 && v < na) {
             X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
@@ -922,7 +934,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             const u32x4 x = in_g[j];
             // counters of this row: base + lane (mod 2^32); the upper 24 bits
             // change at most once inside a row, and then by one
-            const uint32_t base = (uint32_t)(v0 - na) + 2u;
+            const uint32_t base = (uint32_t)(v0 - na) + c1;
             const uint32_t h = base >> 8;
             if (h != hc) {
                 cur = ctr_round2(h, c, rk, te);
@@ -969,11 +981,13 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         partials[d.tile_base + t] = a;
 }
 
-// Kernel variants: GCM; counter mode only; GCM with the GHASH-only pass over
-// whole AAD rows (a kernel of its own so that its extra loop leaves the
-// register allocation of the others alone), used for single messages whose
-// AAD spans at least 64 rows of blocks.
-constexpr int kModeGcm = 0, kModeCtr = 1, kModeGcmAad = 2;
+// Kernel variants (each a kernel of its own, so that the extra work of one
+// leaves the register allocation of the others alone): GCM; counter mode
+// only; GCM with the GHASH-only pass over whole AAD rows, for single messages
+// whose AAD spans at least 64 rows of blocks; GCM with J0 read from device
+// memory, for single messages whose IV is not 96 bits (AAD rows then take the
+// boundary path).
+constexpr int kModeGcm = 0, kModeCtr = 1, kModeGcmAad = 2, kModeGcmJ0 = 3;
 constexpr uint64_t kAadRowsMinBytes = 64 * 64 * 16;
 
 template <int WAVES, bool BATCH, int MODE>
@@ -984,6 +998,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
 {
     constexpr bool GH = MODE != kModeCtr;
     constexpr bool AADROWS = MODE == kModeGcmAad;
+    constexpr bool J0DEV = MODE == kModeGcmJ0;
     __shared__ u32x4 lds_v[8192];  // 128 KiB: GHASH table, then the replicated T-tables
     const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
 
@@ -1055,11 +1070,11 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         const uint64_t t = (uint64_t)first + (uint64_t)wave;
         if (t < d.tile_hi) {
             if (d.nr == 10)
-                wave_tile<10, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<10, GH, AADROWS, J0DEV>(d, t, lds, lk, gk, te0g, partials);
             else if (d.nr == 12)
-                wave_tile<12, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<12, GH, AADROWS, J0DEV>(d, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile<14, GH, AADROWS>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile<14, GH, AADROWS, J0DEV>(d, t, lds, lk, gk, te0g, partials);
         }
     }
 }
@@ -1163,14 +1178,15 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         s = mul_tab4(s, tabs[0]);  // * H
         const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
+        const int tl = (int)d.tag_len;  // T = MSB_t of the full tag
         if (d.op == 0) {
             uint8_t *dst = reinterpret_cast<uint8_t *>(d.tag);
-            for (int k = 0; k < 16; ++k)
+            for (int k = 0; k < tl; ++k)
                 dst[k] = (uint8_t)(tw[k >> 2] >> (8 * (k & 3)));
         } else {
             const uint8_t *exp = reinterpret_cast<const uint8_t *>(d.tag);
             uint32_t diff = 0;
-            for (int k = 0; k < 16; ++k)
+            for (int k = 0; k < tl; ++k)
                 diff |= ((tw[k >> 2] >> (8 * (k & 3))) & 0xffu) ^ exp[k];
             const int32_t ok = diff == 0 ? 1 : 0;
             *reinterpret_cast<int32_t *>(d.ok) = ok;
@@ -1180,6 +1196,38 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
             }
         }
     }
+}
+
+// ---------------------------------------------------------------- J0 for other IV lengths
+
+// J0 = GHASH_H(IV || 0^s || 0^64 || [8*len(IV)]_64) (SP 800-38D sec. 7.1,
+// step 2), by Horner over the IV blocks with the nibble table of H staged in
+// LDS; one workgroup, written to j0_out (16 bytes).
+__global__ __launch_bounds__(64) void k_gcm_j0(IvArg iv, uint64_t slot, u32x4 *j0_out)
+{
+    __shared__ u32x4 tab[512];
+    const GLOBAL_AS u32x4 *src = gptr<const u32x4>(slot + kSlotTab4Off);  // level 0: H
+    u32x4 st[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        st[r] = src[threadIdx.x + 64 * r];
+#pragma unroll
+    for (int r = 0; r < 8; ++r)
+        tab[threadIdx.x + 64 * r] = st[r];
+    lds_barrier();
+    if (threadIdx.x != 0)
+        return;
+    u32x4 y = {0, 0, 0, 0};
+    const uint32_t n = iv.len;
+    for (uint32_t off = 0; off < n; off += 16) {
+        uint32_t w[4] = {0, 0, 0, 0};
+        for (uint32_t k = 0; k < 16 && off + k < n; ++k)
+            w[k >> 2] |= (uint32_t)iv.b[off + k] << (8 * (k & 3));
+        y = mul_tab4(y ^ u32x4{w[0], w[1], w[2], w[3]}, tab);
+    }
+    const uint64_t bits = (uint64_t)n * 8;
+    y = mul_tab4(y ^ u32x4{0u, 0u, bswap32((uint32_t)(bits >> 32)), bswap32((uint32_t)bits)}, tab);
+    *j0_out = y;
 }
 
 // ---------------------------------------------------------------- zero-fill on reject
@@ -1257,6 +1305,9 @@ static hipError_t launch_tiles_w(const MsgDesc *descs, const WorkItem *items, ui
     else if (single->op == 2)
         hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeCtr>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
                            nullptr, n_items, *single, te0, partials, counters);
+    else if (single->j0)
+        hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeGcmJ0>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
+                           nullptr, n_items, *single, te0, partials, counters);
     else if (single->aad_len >= kAadRowsMinBytes)
         hipLaunchKernelGGL((k_gcm_tiles<WAVES, false, kModeGcmAad>), dim3(grid), dim3(WAVES * 64), 0, s, nullptr,
                            nullptr, n_items, *single, te0, partials, counters);
@@ -1311,6 +1362,12 @@ hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *
     else
         hipLaunchKernelGGL(k_gcm_combine<false>, dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, p,
                            counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gcm_j0, dim3(1), dim3(64), 0, s, iv, slot, reinterpret_cast<u32x4 *>(j0_out));
     return hipGetLastError();
 }
 

@@ -122,8 +122,8 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
         return fail(GCM_E_ARG, "NULL argument");
     if (key_len != 16 && key_len != 24 && key_len != 32)
         return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
-    if (iv_len != 12)
-        return fail(GCM_E_IVLEN, "IV length %zu is not 12", iv_len);
+    if (!valid_iv_len(iv_len))
+        return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
     if (len > kMaxLen || aad_len > kMaxAad)
         return fail(GCM_E_TOOLONG, "len %llu / aad_len %llu beyond the SP 800-38D limits", (unsigned long long)len,
                     (unsigned long long)aad_len);
@@ -145,8 +145,9 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
     message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
     const uint64_t B = 1ull << log2B;
     MsgDesc d;
-    fill_desc(&d, op, iv, 0, aad_len, 0, 0, len, (uint64_t)ctx->d_io, (uint64_t)(ctx->d_io + 16), 0, nr, log2B,
-              waves, 0);
+    static const uint8_t zero_iv[12] = {0};
+    fill_desc(&d, op, zero_iv, 0, aad_len, 0, 0, len, (uint64_t)ctx->d_io, (uint64_t)(ctx->d_io + 16), 0, nr,
+              log2B, waves, 0);
     const uint64_t want = ctx->pipe_chunk ? ctx->pipe_chunk : kDefaultChunk;
     const uint64_t tiles_per_chunk = std::max<uint64_t>(1, want / (B * 16));
     rc = ensure_ws_locked(ctx, workspace_bytes_for(d.n_tiles, 1));
@@ -162,6 +163,11 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
         return rc;
     d.slot = (uint64_t)(ctx->d_slots + kSlotBytes * slot);
     d.aad = aad_len ? (uint64_t)ctx->pipe_aad : 0;
+    rc = set_iv(&d, iv, iv_len, ctx->d_ws, sc);
+    if (rc) {
+        (void)pipeline_drain(ctx);
+        return rc;
+    }
     if (aad_len)
         e = hipMemcpyAsync(ctx->pipe_aad, aad_h, aad_len, hipMemcpyHostToDevice, sc);
     if (e == hipSuccess && op == 1)

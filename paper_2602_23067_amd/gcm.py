@@ -143,6 +143,8 @@ def load() -> ctypes.CDLL:
         "gcm_encrypt_host": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp], ctypes.c_int),
         "gcm_decrypt_verify_host": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, i32p], ctypes.c_int),
         "gcm_set_pipeline": ([vp, u64], ctypes.c_int),
+        "gcm_encrypt_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, sz, vp], ctypes.c_int),
+        "gcm_decrypt_verify_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, sz, vp, i32p, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -276,6 +278,23 @@ class Context:
         _check(load().gcm_decrypt_verify(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
                                          0 if aad is None else aad.numel(), _dev(ct), ct.numel(), _host(tag),
                                          _dev(pt), ctypes.byref(acc), _stream(stream)))
+        return acc.value == 1
+
+    def encrypt_ex(self, key: bytes, iv: bytes, aad, pt, ct, tag_len: int = 16, stream=None) -> bytes:
+        """gcm_encrypt with a truncated tag (16, 15, 14, 13, 12, 8 or 4 bytes)."""
+        tag = ctypes.create_string_buffer(16)
+        _check(load().gcm_encrypt_ex(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
+                                     0 if aad is None else aad.numel(), _dev(pt), 0 if pt is None else pt.numel(),
+                                     _dev(ct), tag, tag_len, _stream(stream)))
+        return tag.raw[:tag_len]
+
+    def decrypt_verify_ex(self, key: bytes, iv: bytes, aad, ct, tag: bytes, pt, stream=None) -> bool:
+        """gcm_decrypt_verify against a truncated tag of len(tag) bytes."""
+        acc = ctypes.c_int(-1)
+        _check(load().gcm_decrypt_verify_ex(self._h, _host(key), len(key), _host(iv), len(iv), _dev(aad),
+                                            0 if aad is None else aad.numel(), _dev(ct),
+                                            0 if ct is None else ct.numel(), _host(tag) if tag else None,
+                                            len(tag), _dev(pt), ctypes.byref(acc), _stream(stream)))
         return acc.value == 1
 
     # -------------------------------------------------------- counter mode only, GMAC

@@ -195,9 +195,10 @@ def test_argument_errors(ctx):
     with pytest.raises(gcm.GcmError) as e:
         ctx.encrypt(bytes(20), bytes(12), None, buf, buf)
     assert e.value.code == gcm.GCM_E_KEYLEN
-    with pytest.raises(gcm.GcmError) as e:
-        ctx.encrypt(bytes(16), bytes(16), None, buf, buf)
-    assert e.value.code == gcm.GCM_E_IVLEN
+    for bad_iv in (b"", bytes(1025)):  # IVs of 1..1024 bytes are accepted
+        with pytest.raises(gcm.GcmError) as e:
+            ctx.encrypt(bytes(16), bad_iv, None, buf, buf)
+        assert e.value.code == gcm.GCM_E_IVLEN
     with pytest.raises(gcm.GcmError) as e:
         ctx.encrypt(bytes(16), bytes(12), None, buf[1:33], buf[32:64])
     assert e.value.code == gcm.GCM_E_ARG  # misaligned
