@@ -211,6 +211,39 @@ int gcm_decrypt_verify_host(gcm_ctx *ctx, const uint8_t *key, size_t key_len, co
  * are allocated from the context's budget on first use.  4 KiB..16 GiB. */
 int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes);
 
+/* ---------------------------------------------------------------- streamed messages */
+
+/* One message fed in segments (inputs larger than HBM, or arriving over
+ * time): the (GHASH value, block count) pair of SP 800-38D's GHASH is carried
+ * across calls on the device, with the same tiles, counters and combine as a
+ * single call, so the ciphertext and tag equal gcm_encrypt's on the
+ * concatenated input (the paper's map-reduce across segments, "Scalable
+ * MapReduce for Massive Files").  All calls of one stream object are enqueued
+ * on the given HIP stream in call order without host synchronisation; give
+ * them one stream (or order them).  Key: a registered slot.  IV: 1..1024
+ * bytes.  Decrypt-verify releases plaintext segment by segment; the caller
+ * must not act on it before the final call's flag reads 1 (no zero-fill). */
+typedef struct gcm_stream gcm_stream;
+
+/* op 0 encrypt / 1 decrypt-verify; the AAD (device, 16-byte aligned, may be
+ * empty) is hashed here.  Allocates the stream's device state from the
+ * context budget. */
+int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                     const uint8_t *aad_d, uint64_t aad_len, gcm_stream **out, void *stream);
+
+/* The next `len` bytes of the message: in_d -> out_d (device, 16-byte
+ * aligned, in place allowed).  Every segment but the last must be a multiple
+ * of 16 bytes (GCM_E_ARG afterwards otherwise).  len 0 is a no-op. */
+int gcm_stream_update(gcm_stream *st, const uint8_t *in_d, uint64_t len, uint8_t *out_d, void *stream);
+
+/* Close the message: encrypt writes the 16-byte tag to tag_d (device);
+ * decrypt-verify reads the expected tag from tag_d and writes the int32
+ * accept flag (1/0) to accept_d (device). */
+int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_d, void *stream);
+
+/* Wait for the device, then free the stream's state. */
+int gcm_stream_destroy(gcm_stream *st);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One message of a batch.  All offsets are byte offsets into one device

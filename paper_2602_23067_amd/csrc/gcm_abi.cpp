@@ -361,6 +361,9 @@ void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, ui
     d->fix_lane = 1;  // callers that mix many keys switch large-table fix-ups off per message
     d->j0 = 0;
     d->tag_len = 16;
+    d->ctr_off = 0;
+    d->ystate = 0;
+    d->yout = 0;
 }
 
 bool gcm::valid_iv_len(size_t n) { return n >= 1 && n <= (size_t)kMaxIvBytes; }
@@ -382,7 +385,7 @@ int gcm::set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStrea
     std::memcpy(a.b, iv, iv_len);
     // per message: its T tile partials, E_K(J0), then J0
     uint8_t *j0 = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1) + 16 * (d->tile_base + d->n_tiles + 1);
-    hipError_t e = launch_j0(a, d->slot, j0, s);
+    hipError_t e = launch_j0(a, d->slot, j0, nullptr, s);
     if (e != hipSuccess)
         return fail_hip(e, "J0 kernel launch");
     d->iv[0] = d->iv[1] = d->iv[2] = 0;

@@ -111,7 +111,7 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
 int max_groups_per_cu(int waves);
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
                           uint32_t *counters, hipStream_t s);
-hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, hipStream_t s);
+hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);
 

@@ -71,7 +71,9 @@ struct MsgDesc {
     uint32_t fix_lane;   // 1: per-lane fix-up tables H^(63-l); 0: exponent bits over H^(2^k)
     uint64_t j0;         // device address of J0 (16 bytes) for IVs other than 96 bits; 0: J0 = IV || 0^31 || 1
     uint32_t tag_len;    // tag bytes written (encrypt) or compared (decrypt): 16, or 15, 14, 13, 12, 8, 4
-    uint32_t pad1;
+    uint32_t ctr_off;    // with j0: data blocks that precede this one (a streamed segment), added to the counters
+    uint64_t ystate;     // with j0: GHASH value of the blocks before this segment, XORed into its block 0
+    uint64_t yout;       // the combine writes the segment's GHASH value here instead of forming a tag
 };
 
 // IVs other than 96 bits: J0 = GHASH_H(IV || 0-pad || 0^64 || [len(IV)]_64),

@@ -823,8 +823,12 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
 // p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
 // across the wave.  With GH false the tile is counter mode only (no GHASH,
 // no partial).  AADROWS adds a GHASH-only pass over rows of whole AAD blocks,
-// J0DEV reads J0 from device memory (IVs other than 96 bits) instead of
-// forming IV || 0^31 || 1; both cost the main loop its batching of LDS reads
+// J0DEV reads J0 from device memory (IVs other than 96 bits, streamed
+// segments) instead of forming IV || 0^31 || 1, offsets the counters by
+// d.ctr_off, and continues a streamed GHASH: the running value *d.ystate is
+// XORed into block 0 of the segment, since Horner from state Y over X_1..X_m
+// equals Horner from zero over (X_1 ^ Y), X_2, ..., X_m.  Both options cost
+// the main loop its batching of LDS reads
 // (a run-time counter base, or the extra loop, leaves it fewer registers), so
 // each is compiled only into kernel variants of its own.
 template <int NR, bool GH, bool AADROWS, bool J0DEV>
@@ -843,7 +847,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         iv0 = jw[0];
         iv1 = jw[1];
         iv2 = jw[2];
-        c1 = bswap32(jw[3]) + 1u;
+        c1 = bswap32(jw[3]) + 1u + d.ctr_off;
     }
     AesCtx c;
     {
@@ -897,6 +901,8 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
                       bswap32((uint32_t)cbits)};
         }
+        if (GH && J0DEV && d.ystate && v == 0)
+            X ^= load_const<u32x4>(reinterpret_cast<const void *>(d.ystate));
         if (GH)
             a = ghash_mul8(a, X, lds, gk);
     };
@@ -928,7 +934,8 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         rk = rk_base;
         asm volatile("" : "+s"(rk));
         const int64_t v0 = vbase + 64 * (int64_t)r;
-        if (v0 >= na && v0 + 64 <= na + nfull) {
+        // (a streamed segment's block 0 takes the boundary path, which adds the running GHASH value)
+        if (v0 >= na && v0 + 64 <= na + nfull && !(J0DEV && d.ystate && v0 == 0)) {
             // all 64 lanes hold whole data blocks
             const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
             const u32x4 x = in_g[j];
@@ -1176,6 +1183,10 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
         for (int w = 1; w < kCombineThreads / 64; ++w)
             s ^= red[w];
         s = mul_tab4(s, tabs[0]);  // * H
+        if (d.yout) {  // a streamed segment: hand on its GHASH value
+            *reinterpret_cast<u32x4 *>(d.yout) = s;
+            return;
+        }
         const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         const int tl = (int)d.tag_len;  // T = MSB_t of the full tag
@@ -1203,8 +1214,19 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
 // J0 = GHASH_H(IV || 0^s || 0^64 || [8*len(IV)]_64) (SP 800-38D sec. 7.1,
 // step 2), by Horner over the IV blocks with the nibble table of H staged in
 // LDS; one workgroup, written to j0_out (16 bytes).
-__global__ __launch_bounds__(64) void k_gcm_j0(IvArg iv, uint64_t slot, u32x4 *j0_out)
+__global__ __launch_bounds__(64) void k_gcm_j0(IvArg iv, uint64_t slot, u32x4 *j0_out, u32x4 *y_zero)
 {
+    if (y_zero && threadIdx.x == 0)
+        *y_zero = u32x4{0, 0, 0, 0};  // a new stream's GHASH value
+    if (iv.len == 12) {  // J0 = IV || 0^31 || 1
+        if (threadIdx.x == 0) {
+            uint32_t w[3] = {0, 0, 0};
+            for (int k = 0; k < 12; ++k)
+                w[k >> 2] |= (uint32_t)iv.b[k] << (8 * (k & 3));
+            *j0_out = u32x4{w[0], w[1], w[2], 0x01000000u};
+        }
+        return;
+    }
     __shared__ u32x4 tab[512];
     const GLOBAL_AS u32x4 *src = gptr<const u32x4>(slot + kSlotTab4Off);  // level 0: H
     u32x4 st[8];
@@ -1365,9 +1387,10 @@ hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *
     return hipGetLastError();
 }
 
-hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, hipStream_t s)
+hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_gcm_j0, dim3(1), dim3(64), 0, s, iv, slot, reinterpret_cast<u32x4 *>(j0_out));
+    hipLaunchKernelGGL(k_gcm_j0, dim3(1), dim3(64), 0, s, iv, slot, reinterpret_cast<u32x4 *>(j0_out),
+                       reinterpret_cast<u32x4 *>(y_zero));
     return hipGetLastError();
 }
 

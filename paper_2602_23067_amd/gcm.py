@@ -144,6 +144,10 @@ def load() -> ctypes.CDLL:
         "gcm_decrypt_verify_host": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, i32p], ctypes.c_int),
         "gcm_set_pipeline": ([vp, u64], ctypes.c_int),
         "gcm_encrypt_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, sz, vp], ctypes.c_int),
+        "gcm_stream_begin": ([vp, u32, u32, vp, sz, vp, u64, ctypes.POINTER(vp), vp], ctypes.c_int),
+        "gcm_stream_update": ([vp, vp, u64, vp, vp], ctypes.c_int),
+        "gcm_stream_final": ([vp, vp, vp, vp], ctypes.c_int),
+        "gcm_stream_destroy": ([vp], ctypes.c_int),
         "gcm_decrypt_verify_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, sz, vp, i32p, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -297,6 +301,13 @@ class Context:
                                             len(tag), _dev(pt), ctypes.byref(acc), _stream(stream)))
         return acc.value == 1
 
+    # -------------------------------------------------------- streamed messages
+    def stream_begin(self, op: int, slot: int, iv: bytes, aad=None, stream=None) -> "GcmStream":
+        h = ctypes.c_void_p()
+        _check(load().gcm_stream_begin(self._h, op, slot, _host(iv), len(iv), _dev(aad),
+                                       0 if aad is None else aad.numel(), ctypes.byref(h), _stream(stream)))
+        return GcmStream(h)
+
     # -------------------------------------------------------- counter mode only, GMAC
     def ctr_xcrypt(self, key: bytes, iv: bytes, src, dst, stream=None) -> None:
         """AES-CTR with GCM's counters (no tag); encrypts and decrypts."""
@@ -383,6 +394,31 @@ class Context:
 
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
         _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))
+
+
+class GcmStream:
+    """A message fed in segments (see gcm_stream_* in the C header)."""
+
+    def __init__(self, h):
+        self._h = h
+
+    def update(self, src, dst, stream=None) -> None:
+        _check(load().gcm_stream_update(self._h, _dev(src), src.numel(), _dev(dst), _stream(stream)))
+
+    def final(self, tag_d, accept_d=None, stream=None) -> None:
+        _check(load().gcm_stream_final(self._h, _dev(tag_d), None if accept_d is None else accept_d.data_ptr(),
+                                       _stream(stream)))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().gcm_stream_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ------------------------------------------------------------------ batches

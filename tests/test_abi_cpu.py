@@ -25,7 +25,8 @@ def test_header_declares_the_boundary():
     for need in ("gcm_ctx_create", "gcm_ctx_destroy", "gcm_last_error", "gcm_encrypt", "gcm_decrypt_verify",
                  "gcm_key_register", "gcm_key_release", "gcm_encrypt_async", "gcm_decrypt_verify_async",
                  "gcm_ctr_xcrypt", "gcm_ctr_async", "gcm_gmac", "gcm_encrypt_host", "gcm_decrypt_verify_host",
-                 "gcm_set_pipeline", "gcm_encrypt_ex", "gcm_decrypt_verify_ex"):
+                 "gcm_set_pipeline", "gcm_encrypt_ex", "gcm_decrypt_verify_ex",
+                 "gcm_stream_begin", "gcm_stream_update", "gcm_stream_final", "gcm_stream_destroy"):
         assert need in names
 
 

@@ -1,0 +1,155 @@
+"""GPU parity of the streamed-message API: a message fed in device segments
+must give the oracle's ciphertext and tag for the concatenated input, bit for
+bit, for any segmentation."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2602_23067_amd import gcm  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+from gpu_util import host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = gcm.Context(device=0, key_slots=16)
+    yield c
+    c.close()
+
+
+def _stream_encrypt(ctx, slot, iv, aad, pt, cuts, stream=None):
+    st = ctx.stream_begin(0, slot, iv, to_dev(aad) if aad.size else None, stream)
+    try:
+        outs = []
+        for a, b in zip([0] + cuts, cuts + [pt.size]):
+            src = to_dev(pt[a:b])
+            dst = torch.empty_like(src)
+            st.update(src, dst, stream)
+            outs.append(dst)
+        tag_d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        st.final(tag_d, None, stream)
+        torch.cuda.synchronize()
+        ct = np.concatenate([host(o) for o in outs]) if outs else np.zeros(0, np.uint8)
+        return ct, bytes(host(tag_d))
+    finally:
+        st.close()
+
+
+CASES = [
+    # (seed, key_len, iv_len, aad_len, segment lengths)
+    (1, 16, 12, 0, [16]),
+    (2, 32, 12, 5000, [1 << 20, (1 << 20) + 5]),
+    (3, 24, 20, 77, [4096 * 3, 16, 1000 * 16, 777]),
+    (4, 32, 12, 2880, [4096] * 50 + [33]),
+    (5, 16, 7, 16, [64 * 16 * 5, 64 * 16 * 3, 15]),
+    (6, 32, 12, 100_000, []),  # AAD only: a streamed GMAC
+    (7, 16, 12, 0, []),  # nothing at all: T = E_K(J0)
+]
+
+
+@pytest.mark.parametrize("seed,key_len,iv_len,aad_len,segs", CASES)
+def test_stream_encrypt_matches_oracle(ctx, seed, key_len, iv_len, aad_len, segs):
+    r = np.random.default_rng(6000 + seed)
+    key, iv = r.bytes(key_len), r.bytes(iv_len)
+    aad = r.integers(0, 256, aad_len, dtype=np.uint8)
+    pt = r.integers(0, 256, sum(segs), dtype=np.uint8)
+    cuts = list(np.cumsum(segs)[:-1]) if segs else []
+    rct, rtag = oracle.gcm_encrypt(key, iv, aad, pt)
+    print(f"stream seed={seed} segments={len(segs)} n={pt.size}", flush=True)
+    slot = ctx.key_register(key)
+    try:
+        for shape in [(0, 0, 0), (8, 16, 0)]:
+            ctx.set_launch(*shape)
+            try:
+                ct, tag = _stream_encrypt(ctx, slot, iv, aad, pt, [int(c) for c in cuts])
+            finally:
+                ctx.set_launch(0, 0, 0)
+            assert np.array_equal(ct, rct), f"ciphertext, shape {shape}"
+            assert tag == rtag, f"tag, shape {shape}"
+    finally:
+        ctx.key_release(slot)
+
+
+def test_stream_decrypt_verify_and_tamper(ctx):
+    r = np.random.default_rng(6100)
+    key, iv = r.bytes(32), r.bytes(12)
+    aad = r.integers(0, 256, 300, dtype=np.uint8)
+    pt = r.integers(0, 256, 3 * (1 << 20) + 3, dtype=np.uint8)
+    rct, rtag = oracle.gcm_encrypt(key, iv, aad, pt)
+    slot = ctx.key_register(key)
+    s = torch.cuda.Stream()
+    torch.cuda.current_stream().synchronize()
+    try:
+        for tag in (rtag, bytes([rtag[0] ^ 0x80]) + rtag[1:]):
+            # every buffer is made on the current stream and kept alive until
+            # `s` has finished with it
+            aad_d = to_dev(aad)
+            srcs = [to_dev(rct[a:b]) for a, b in ((0, 1 << 20), (1 << 20, 3 << 20), (3 << 20, pt.size))]
+            outs = [torch.empty_like(x) for x in srcs]
+            s.wait_stream(torch.cuda.current_stream())
+            st = ctx.stream_begin(1, slot, iv, aad_d, stream=s)
+            for src, dst in zip(srcs, outs):
+                st.update(src, dst, stream=s)
+            tag_d = to_dev(np.frombuffer(tag, np.uint8))
+            ok_d = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+            s.wait_stream(torch.cuda.current_stream())
+            st.final(tag_d, ok_d, stream=s)
+            s.synchronize()
+            st.close()
+            ok = int(host(ok_d)[0])
+            if tag == rtag:
+                assert ok == 1
+                assert np.array_equal(np.concatenate([host(o) for o in outs]), pt)
+            else:
+                assert ok == 0
+    finally:
+        ctx.key_release(slot)
+
+
+def test_stream_counter_wraps_across_segments(ctx):
+    r = np.random.default_rng(6200)
+    key = r.bytes(16)
+    for _ in range(400_000):
+        iv = r.bytes(12 + 4)  # a 16-byte IV: J0 from GHASH, arbitrary counter
+        c0 = int.from_bytes(oracle.gcm_j0(key, iv)[12:], "big")
+        if c0 > (1 << 32) - 60_000:
+            break
+    else:
+        pytest.fail("no IV with a J0 counter near 2^32 found")
+    pt = r.integers(0, 256, 65536 * 16 + 1, dtype=np.uint8)
+    rct, rtag = oracle.gcm_encrypt(key, iv, b"", pt)
+    slot = ctx.key_register(key)
+    try:
+        ct, tag = _stream_encrypt(ctx, slot, iv, np.zeros(0, np.uint8), pt, [16 * 30_000, 16 * 61_000])
+    finally:
+        ctx.key_release(slot)
+    assert np.array_equal(ct, rct) and tag == rtag
+
+
+def test_stream_misuse_errors(ctx):
+    slot = ctx.key_register(bytes(16))
+    try:
+        st = ctx.stream_begin(0, slot, bytes(12))
+        buf = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        st.update(buf[:32], buf[:32])
+        st.update(buf[:17], buf[:17])  # a partial block: must be the last segment
+        with pytest.raises(gcm.GcmError) as e:
+            st.update(buf[:16], buf[:16])
+        assert e.value.code == gcm.GCM_E_ARG
+        tag_d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        st.final(tag_d)
+        with pytest.raises(gcm.GcmError) as e:
+            st.final(tag_d)
+        assert e.value.code == gcm.GCM_E_ARG
+        st.close()
+        with pytest.raises(gcm.GcmError) as e:
+            ctx.stream_begin(2, slot, bytes(12))
+        assert e.value.code == gcm.GCM_E_ARG
+    finally:
+        torch.cuda.synchronize()
+        ctx.key_release(slot)
