@@ -244,6 +244,55 @@ int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_d, void *st
 /* Wait for the device, then free the stream's state. */
 int gcm_stream_destroy(gcm_stream *st);
 
+/* ---------------------------------------------------------------- authenticated FITS container */
+
+/* The paper's container ("Authenticated FITS File Format", "Context Binding
+ * via Associated Data (AAD)", "Policy Enforcement and Granular Access") for a
+ * 2-D FITS image (primary HDU, BITPIX 8/16/32/64/-32/-64, NAXIS = 2):
+ *   HDU 0, NAXIS = 0: NONCE_H, NONCE_D (hex), ORIG_BPX, ORIG_NAX, ORIG_NA1,
+ *     ORIG_NA2 (the original BITPIX, NAXIS, NAXIS1, NAXIS2), HIERARCH
+ *     AUTHTAG_H / AUTHTAG_D (hex; the names exceed eight characters), and
+ *     ENCHDR: the original header blocks (2880-byte multiple, END included)
+ *     encrypted under the header key with AAD = NONCE_H, base64, in a long
+ *     string continued over CONTINUE cards (LONGSTRN = 'OGIP 1.0');
+ *   HDU 1: a one-row BINTABLE, TFORM1 = '<N>B', whose cell is the N pixel
+ *     bytes encrypted under the data key with
+ *     AAD_D = NONCE_D || dec(BITPIX) || dec(NAXIS) || dec(NAXIS1) || dec(NAXIS2)
+ *     (raw nonce bytes, then each value in strict ASCII decimal, e.g. -32 ->
+ *     the three bytes "-32", without separators).
+ * Both GCM computations run on the GPU (through the host pipeline).  No
+ * CHECKSUM/DATASUM cards are written. */
+typedef struct gcm_fits_result {
+    uint8_t *data;        /* FITS bytes (malloc'd by the library; gcm_fits_free) */
+    uint64_t size;
+    int32_t error_code;   /* GCM_OK, or the negative code the call returned */
+    int32_t warning_code; /* decrypt: 0 full access; 1 header fallback (header key missing or wrong:
+                             a minimal header rebuilt from ORIG_*); 2 payload suppressed (data key
+                             missing or wrong, or pixels / ORIG_* / NONCE_D tampered: pixels zeroed);
+                             3 both */
+} gcm_fits_result;
+
+/* Encrypt FITS file bytes (host) into a container (out->data, host).  Keys:
+ * 16, 24 or 32 bytes each; nonces: 12 bytes each (see gcm_fits_nonce).
+ * Returns GCM_OK or a negative code (also stored in out->error_code). */
+int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits_len, const uint8_t *key_h, size_t key_h_len,
+                     const uint8_t *key_d, size_t key_d_len, const uint8_t nonce_h[12], const uint8_t nonce_d[12],
+                     gcm_fits_result *out);
+
+/* Decrypt a container with the keys the caller holds (either may be NULL):
+ * out->data receives a FITS file whose header is the authenticated original
+ * (else the minimal ORIG_* header) and whose pixels are the authenticated
+ * plaintext (else zeros), with out->warning_code as above (the paper's
+ * FitsOperationResult).  A malformed container is GCM_E_ARG. */
+int gcm_fits_decrypt(gcm_ctx *ctx, const uint8_t *container, uint64_t len, const uint8_t *key_h, size_t key_h_len,
+                     const uint8_t *key_d, size_t key_d_len, gcm_fits_result *out);
+
+/* Free out->data of a result. */
+void gcm_fits_free(gcm_fits_result *r);
+
+/* 12 bytes from the kernel's entropy pool (getrandom), for NONCE_H / NONCE_D. */
+int gcm_fits_nonce(uint8_t out[12]);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One message of a batch.  All offsets are byte offsets into one device

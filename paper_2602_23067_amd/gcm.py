@@ -89,6 +89,13 @@ class Job(ctypes.Structure):
     ]
 
 
+class FitsResult(ctypes.Structure):
+    """Mirror of ``gcm_fits_result``."""
+
+    _fields_ = [("data", ctypes.c_void_p), ("size", ctypes.c_uint64), ("error_code", ctypes.c_int32),
+                ("warning_code", ctypes.c_int32)]
+
+
 class GcmError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"[{code}] {msg}")
@@ -145,6 +152,10 @@ def load() -> ctypes.CDLL:
         "gcm_set_pipeline": ([vp, u64], ctypes.c_int),
         "gcm_encrypt_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, vp, sz, vp], ctypes.c_int),
         "gcm_stream_begin": ([vp, u32, u32, vp, sz, vp, u64, ctypes.POINTER(vp), vp], ctypes.c_int),
+        "gcm_fits_encrypt": ([vp, vp, u64, vp, sz, vp, sz, vp, vp, ctypes.POINTER(FitsResult)], ctypes.c_int),
+        "gcm_fits_decrypt": ([vp, vp, u64, vp, sz, vp, sz, ctypes.POINTER(FitsResult)], ctypes.c_int),
+        "gcm_fits_free": ([ctypes.POINTER(FitsResult)], None),
+        "gcm_fits_nonce": ([vp], ctypes.c_int),
         "gcm_stream_update": ([vp, vp, u64, vp, vp], ctypes.c_int),
         "gcm_stream_final": ([vp, vp, vp, vp], ctypes.c_int),
         "gcm_stream_destroy": ([vp], ctypes.c_int),
@@ -301,6 +312,34 @@ class Context:
                                             len(tag), _dev(pt), ctypes.byref(acc), _stream(stream)))
         return acc.value == 1
 
+    # -------------------------------------------------------- authenticated FITS container
+    def fits_encrypt(self, fits_bytes: bytes, key_h: bytes, key_d: bytes, nonce_h: bytes = None,
+                     nonce_d: bytes = None) -> bytes:
+        """The paper's two-HDU container for a 2-D FITS image (nonces drawn
+        from the entropy pool when not given)."""
+        nonce_h = nonce_h if nonce_h is not None else fits_nonce()
+        nonce_d = nonce_d if nonce_d is not None else fits_nonce()
+        r = FitsResult()
+        src = _host(fits_bytes)
+        try:
+            _check(load().gcm_fits_encrypt(self._h, src, len(fits_bytes), _host(key_h), len(key_h), _host(key_d),
+                                           len(key_d), _host(nonce_h), _host(nonce_d), ctypes.byref(r)))
+            return ctypes.string_at(r.data, r.size)
+        finally:
+            load().gcm_fits_free(ctypes.byref(r))
+
+    def fits_decrypt(self, container: bytes, key_h: bytes = None, key_d: bytes = None):
+        """(FITS bytes, warning_code): 0 full, 1 header fallback, 2 payload suppressed, 3 both."""
+        r = FitsResult()
+        src = _host(container)
+        try:
+            _check(load().gcm_fits_decrypt(self._h, src, len(container), _host(key_h) if key_h else None,
+                                           len(key_h) if key_h else 0, _host(key_d) if key_d else None,
+                                           len(key_d) if key_d else 0, ctypes.byref(r)))
+            return ctypes.string_at(r.data, r.size), r.warning_code
+        finally:
+            load().gcm_fits_free(ctypes.byref(r))
+
     # -------------------------------------------------------- streamed messages
     def stream_begin(self, op: int, slot: int, iv: bytes, aad=None, stream=None) -> "GcmStream":
         h = ctypes.c_void_p()
@@ -394,6 +433,13 @@ class Context:
 
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
         _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))
+
+
+def fits_nonce() -> bytes:
+    """12 bytes from the kernel's entropy pool."""
+    b = ctypes.create_string_buffer(12)
+    _check(load().gcm_fits_nonce(b))
+    return b.raw
 
 
 class GcmStream:

@@ -77,6 +77,44 @@ def fits_image_bytes(rng: np.random.Generator, ny: int, nx: int, mean: float = 1
     return out
 
 
+def fits_file(rng: np.random.Generator, ny: int, nx: int, bitpix: int = -32, n_sources: int = 20) -> bytes:
+    """A complete single-HDU FITS image file: a primary header with the
+    mandatory keywords, a simple tangent-plane WCS, OBJECT / EXPTIME / DATE-OBS
+    cards and a comment, then the big-endian pixels (Gaussian sky noise with
+    point sources, cast to BITPIX) zero-padded to a multiple of 2880 bytes.
+    The stand-in for the paper's 256x256 float32 test file with
+    representative WCS metadata."""
+    def card(text: str) -> str:
+        return text.ljust(CARD)
+
+    def kv(name: str, value: str) -> str:
+        return card(name.ljust(8) + "= " + value)
+
+    def num(name: str, v) -> str:
+        return kv(name, str(v).rjust(20))
+
+    def sval(name: str, v: str) -> str:
+        return kv(name, "'" + v.ljust(8) + "'")
+
+    cards = [kv("SIMPLE", "T".rjust(20)), num("BITPIX", bitpix), num("NAXIS", 2), num("NAXIS1", nx),
+             num("NAXIS2", ny), sval("CTYPE1", "RA---TAN"), sval("CTYPE2", "DEC--TAN"),
+             num("CRPIX1", f"{nx / 2 + 0.5:.1f}"), num("CRPIX2", f"{ny / 2 + 0.5:.1f}"),
+             num("CRVAL1", f"{rng.uniform(0, 360):.6f}"), num("CRVAL2", f"{rng.uniform(-90, 90):.6f}"),
+             num("CDELT1", "-0.000138889"), num("CDELT2", "0.000138889"), sval("OBJECT", "SYNTH_FIELD"),
+             num("EXPTIME", f"{rng.uniform(10, 600):.1f}"), sval("DATE-OBS", "2025-01-15T03:12:45"),
+             card("COMMENT   synthetic sky image: Gaussian noise and point sources"), card("END")]
+    header = "".join(cards).encode("ascii")
+    header += b" " * ((-len(header)) % FITS_BLOCK)
+    img = fits_image_bytes(rng, ny, nx, n_sources=n_sources)[:ny * nx * 4].view(">f4").astype(np.float64)
+    dt = {8: ">u1", 16: ">i2", 32: ">i4", 64: ">i8", -32: ">f4", -64: ">f8"}[bitpix]
+    if bitpix > 0:
+        hi = {8: 255, 16: 32767, 32: 2**31 - 1, 64: 2**62}[bitpix]
+        img = np.clip(np.rint(img), 0, hi)
+    data = img.astype(dt).tobytes()
+    data += bytes((-len(data)) % FITS_BLOCK)
+    return header + data
+
+
 @dataclass
 class Message:
     key: bytes
