@@ -317,15 +317,22 @@ void append_cards(std::vector<uint8_t> *out, const std::vector<std::string> &car
     out->resize(start + pad_to_block(out->size() - start), ' ');
 }
 
-int result_buffer(gcm_fits_result *r, std::vector<uint8_t> &&bytes)
+// the result buffer is allocated once at its final size and filled in place
+// (payloads are encrypted or decrypted straight into it)
+int result_alloc(gcm_fits_result *r, uint64_t bytes)
 {
-    r->data = static_cast<uint8_t *>(std::malloc(bytes.size() ? bytes.size() : 1));
+    r->data = static_cast<uint8_t *>(std::malloc(bytes ? bytes : 1));
     if (!r->data)
-        return fail(GCM_E_NOMEM, "host allocation of %zu bytes failed", bytes.size());
-    if (!bytes.empty())
-        std::memcpy(r->data, bytes.data(), bytes.size());
-    r->size = bytes.size();
+        return fail(GCM_E_NOMEM, "host allocation of %llu bytes failed", (unsigned long long)bytes);
+    r->size = bytes;
     return GCM_OK;
+}
+
+std::vector<uint8_t> card_bytes(const std::vector<std::string> &cards)
+{
+    std::vector<uint8_t> b;
+    append_cards(&b, cards);
+    return b;
 }
 
 int finish(gcm_fits_result *r, int rc)
@@ -379,17 +386,32 @@ extern "C" int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits
     if (h.bytes + nd > fits_len)
         return finish(out, fail(GCM_E_ARG, "FITS data shorter than NAXIS1 x NAXIS2 x |BITPIX|/8"));
 
-    // header and pixels encrypted on the GPU (host-to-host pipeline)
-    std::vector<uint8_t> ct_h(h.bytes), ct_d(nd);
+    // header encrypted on the GPU (host pipeline); the HDU 0 cards need its tag
+    std::vector<uint8_t> ct_h(h.bytes);
     uint8_t tag_h[16], tag_d[16];
     int rc = gcm_encrypt_host(ctx, key_h, key_h_len, nonce_h, 12, nonce_h, 12, fits, h.bytes, ct_h.data(), tag_h);
-    if (rc == GCM_OK) {
-        const std::vector<uint8_t> aad = data_aad(nonce_d, s);
-        rc = gcm_encrypt_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), fits + h.bytes, nd,
-                              ct_d.data(), tag_d);
-    }
     if (rc)
         return finish(out, rc);
+    // the HDU 0 and HDU 1 headers have fixed sizes (the tags are fixed-width
+    // hex), so the pixels are encrypted straight into their final place
+    const std::string enc = b64_encode(ct_h.data(), ct_h.size());
+    constexpr size_t kChunk = 64;
+    const size_t enc_cards = enc.empty() ? 1 : (enc.size() + kChunk - 1) / kChunk;
+    const size_t h0_bytes = pad_to_block((14 + enc_cards) * kCard), h1_bytes = kBlock;
+    rc = result_alloc(out, h0_bytes + h1_bytes + pad_to_block(nd));
+    if (rc)
+        return finish(out, rc);
+    uint8_t *blob = out->data + h0_bytes + h1_bytes;
+    {
+        const std::vector<uint8_t> aad = data_aad(nonce_d, s);
+        rc = gcm_encrypt_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), fits + h.bytes, nd, blob,
+                              tag_d);
+    }
+    if (rc) {
+        gcm_fits_free(out);
+        return finish(out, rc);
+    }
+    std::memset(blob + nd, 0, pad_to_block(nd) - nd);
 
     std::vector<std::string> c0 = {card_logical("SIMPLE", true), card_int("BITPIX", 8), card_int("NAXIS", 0),
                                    card_logical("EXTEND", true), card_str("LONGSTRN", "OGIP 1.0"),
@@ -398,8 +420,6 @@ extern "C" int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits
                                    card_int("ORIG_NA1", s.naxis1), card_int("ORIG_NA2", s.naxis2),
                                    card_hierarch_str("AUTHTAG_H", hex(tag_h, 16)),
                                    card_hierarch_str("AUTHTAG_D", hex(tag_d, 16))};
-    const std::string enc = b64_encode(ct_h.data(), ct_h.size());
-    constexpr size_t kChunk = 64;
     for (size_t i = 0; i < enc.size() || i == 0; i += kChunk) {
         const bool last = i + kChunk >= enc.size();
         const std::string part = enc.substr(i, kChunk) + (last ? "" : "&");
@@ -410,15 +430,15 @@ extern "C" int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits
                                    card_int("NAXIS1", (long long)nd), card_int("NAXIS2", 1), card_int("PCOUNT", 0),
                                    card_int("GCOUNT", 1), card_int("TFIELDS", 1), card_str("TTYPE1", "BLOB"),
                                    card_str("TFORM1", std::to_string(nd) + "B"), card_raw("END")};
-    std::vector<uint8_t> file;
-    append_cards(&file, c0);
-    append_cards(&file, c1);
-    const size_t d0 = file.size();
-    file.insert(file.end(), ct_d.begin(), ct_d.end());
-    file.resize(d0 + pad_to_block(nd), 0);
-    rc = result_buffer(out, std::move(file));
+    const std::vector<uint8_t> b0 = card_bytes(c0), b1 = card_bytes(c1);
+    if (b0.size() != h0_bytes || b1.size() != h1_bytes) {  // the fixed layout above must hold
+        gcm_fits_free(out);
+        return finish(out, fail(GCM_E_ARG, "internal: container header sizes %zu/%zu", b0.size(), b1.size()));
+    }
+    std::memcpy(out->data, b0.data(), h0_bytes);
+    std::memcpy(out->data + h0_bytes, b1.data(), h1_bytes);
     out->warning_code = 0;
-    return finish(out, rc);
+    return finish(out, GCM_OK);
 }
 
 extern "C" int gcm_fits_decrypt(gcm_ctx *ctx, const uint8_t *container, uint64_t len, const uint8_t *key_h,
@@ -480,28 +500,31 @@ extern "C" int gcm_fits_decrypt(gcm_ctx *ctx, const uint8_t *container, uint64_t
         warn |= 1;
     }
     const uint64_t nout = data_bytes(so);
-    // pixels: authenticated plaintext, else zeros (payload suppression)
-    std::vector<uint8_t> file(std::move(header));
-    const size_t d0 = file.size();
-    file.resize(d0 + pad_to_block(nout), 0);
+    const size_t d0 = header.size();
+    int rc = result_alloc(out, d0 + pad_to_block(nout));
+    if (rc)
+        return finish(out, rc);
+    std::memcpy(out->data, header.data(), d0);
+    uint8_t *pix = out->data + d0;
+    // pixels: authenticated plaintext, else zeros (payload suppression); a blob
+    // whose size differs from the output shape cannot authenticate
     int ok_d = 0;
-    if (key_d) {
+    if (key_d && (uint64_t)nblob == nout) {
         const std::vector<uint8_t> aad = data_aad(nonce_d, s);
-        std::vector<uint8_t> pt((size_t)nblob);
-        int rc = gcm_decrypt_verify_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), ct_d,
-                                         (uint64_t)nblob, tag_d, pt.data(), &ok_d);
-        if (rc && rc != GCM_E_KEYLEN)
+        rc = gcm_decrypt_verify_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), ct_d, nout, tag_d,
+                                     pix, &ok_d);
+        if (rc && rc != GCM_E_KEYLEN) {
+            gcm_fits_free(out);
             return finish(out, rc);
+        }
         if (rc == GCM_E_KEYLEN)
             ok_d = 0;
-        if (ok_d && (uint64_t)nblob == nout)
-            std::memcpy(file.data() + d0, pt.data(), nout);
-        else
-            ok_d = 0;
     }
-    if (!ok_d)
+    if (!ok_d) {
+        std::memset(pix, 0, nout);
         warn |= 2;
-    int rc = result_buffer(out, std::move(file));
+    }
+    std::memset(pix + nout, 0, pad_to_block(nout) - nout);
     out->warning_code = warn;
-    return finish(out, rc);
+    return finish(out, GCM_OK);
 }

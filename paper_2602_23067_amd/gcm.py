@@ -320,9 +320,9 @@ class Context:
         nonce_h = nonce_h if nonce_h is not None else fits_nonce()
         nonce_d = nonce_d if nonce_d is not None else fits_nonce()
         r = FitsResult()
-        src = _host(fits_bytes)
+        src = fits_bytes if isinstance(fits_bytes, bytes) else bytes(fits_bytes)  # passed without a copy
         try:
-            _check(load().gcm_fits_encrypt(self._h, src, len(fits_bytes), _host(key_h), len(key_h), _host(key_d),
+            _check(load().gcm_fits_encrypt(self._h, src, len(src), _host(key_h), len(key_h), _host(key_d),
                                            len(key_d), _host(nonce_h), _host(nonce_d), ctypes.byref(r)))
             return ctypes.string_at(r.data, r.size)
         finally:
@@ -331,9 +331,9 @@ class Context:
     def fits_decrypt(self, container: bytes, key_h: bytes = None, key_d: bytes = None):
         """(FITS bytes, warning_code): 0 full, 1 header fallback, 2 payload suppressed, 3 both."""
         r = FitsResult()
-        src = _host(container)
+        src = container if isinstance(container, bytes) else bytes(container)  # passed without a copy
         try:
-            _check(load().gcm_fits_decrypt(self._h, src, len(container), _host(key_h) if key_h else None,
+            _check(load().gcm_fits_decrypt(self._h, src, len(src), _host(key_h) if key_h else None,
                                            len(key_h) if key_h else 0, _host(key_d) if key_d else None,
                                            len(key_d) if key_d else 0, ctypes.byref(r)))
             return ctypes.string_at(r.data, r.size), r.warning_code
