@@ -133,3 +133,11 @@ def test_context_binding_detects_tampered_structure_and_payload():
     bad[pos] = ord("0") if bad[pos] != ord("0") else ord("1")
     _, warn = fc.decrypt(bytes(bad), kh, kd)
     assert warn == 1
+
+
+def test_data_aad_concatenation_is_not_prefix_free():
+    """The paper's literal AAD_D admits equal-size reshapes (documented
+    limitation of the format): 5 x 550 and 55 x 50 hash the same bytes."""
+    nonce = bytes(12)
+    assert fc.data_aad(nonce, -32, 2, 5, 550) == fc.data_aad(nonce, -32, 2, 55, 50)
+    assert 5 * 550 == 55 * 50
