@@ -302,11 +302,16 @@ uint64_t data_bytes(const Structure &s)
     return (uint64_t)(b / 8) * (uint64_t)s.naxis1 * (uint64_t)s.naxis2;
 }
 
+// a 2-D image whose pixel bytes fit the GCM length limit (so no size below overflows)
 bool valid_structure(const Structure &s)
 {
     const long long b = s.bitpix;
     const bool bp = b == 8 || b == 16 || b == 32 || b == 64 || b == -32 || b == -64;
-    return bp && s.naxis == 2 && s.naxis1 >= 0 && s.naxis2 >= 0 && s.naxis1 < (1ll << 32) && s.naxis2 < (1ll << 32);
+    if (!bp || s.naxis != 2 || s.naxis1 < 0 || s.naxis2 < 0 || s.naxis1 > kMaxLen || s.naxis2 > kMaxLen)
+        return false;
+    const unsigned __int128 n = (unsigned __int128)(uint64_t)((b < 0 ? -b : b) / 8) * (uint64_t)s.naxis1 *
+                                (uint64_t)s.naxis2;
+    return n <= kMaxLen;
 }
 
 void append_cards(std::vector<uint8_t> *out, const std::vector<std::string> &cards)
@@ -383,7 +388,7 @@ extern "C" int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits
         !get_int(h, "NAXIS2", &s.naxis2) || !valid_structure(s))
         return finish(out, fail(GCM_E_ARG, "primary HDU must be a 2-D image (BITPIX 8/16/32/64/-32/-64)"));
     const uint64_t nd = data_bytes(s);
-    if (h.bytes + nd > fits_len)
+    if (nd > fits_len || h.bytes > fits_len - nd)
         return finish(out, fail(GCM_E_ARG, "FITS data shorter than NAXIS1 x NAXIS2 x |BITPIX|/8"));
 
     // header encrypted on the GPU (host pipeline); the HDU 0 cards need its tag
@@ -464,8 +469,8 @@ extern "C" int gcm_fits_decrypt(gcm_ctx *ctx, const uint8_t *container, uint64_t
     // the blob: N bytes as the BINTABLE declares them
     long long nblob = -1;
     std::string tform;
-    if (!get_int(h1, "NAXIS1", &nblob) || nblob < 0 || !get_str(h1, "TFORM1", &tform) ||
-        tform != std::to_string(nblob) + "B" || h0.bytes + h1.bytes + (uint64_t)nblob > len)
+    if (!get_int(h1, "NAXIS1", &nblob) || nblob < 0 || (uint64_t)nblob > len || !get_str(h1, "TFORM1", &tform) ||
+        tform != std::to_string(nblob) + "B" || h0.bytes + h1.bytes > len - (uint64_t)nblob)
         return finish(out, fail(GCM_E_ARG, "container blob is not a %lld-byte TFORM1 cell", nblob));
     std::vector<uint8_t> ct_h;
     if (!b64_decode(enc, &ct_h) || ct_h.empty() || ct_h.size() % kBlock)

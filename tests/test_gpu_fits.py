@@ -104,3 +104,20 @@ def test_nonces_and_errors(ctx):
     with pytest.raises(gcm.GcmError) as e:
         ctx.fits_decrypt(c1[:len(c1) - 2880], kh, kd)  # truncated blob
     assert e.value.code == gcm.GCM_E_ARG
+    # sizes whose products overflow 64 bits, in an input image and in a container
+    huge = f.replace(fc._int("NAXIS1", 16).encode(), fc._int("NAXIS1", 1 << 40).encode(), 1)
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.fits_encrypt(huge, kh, kd)
+    assert e.value.code == gcm.GCM_E_ARG
+    cards0, size0 = fc.parse_header(c1)
+    cards1, _ = fc.parse_header(c1, size0)
+    big = c1.replace(fc._int("ORIG_NA1", 16).encode(), fc._int("ORIG_NA1", (1 << 62) + 1).encode(), 1)
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.fits_decrypt(big, kh, kd)
+    assert e.value.code == gcm.GCM_E_ARG
+    n1 = int(fc._value(cards1, "NAXIS1"))
+    blob = c1.replace(fc._int("NAXIS1", n1).encode(), fc._int("NAXIS1", (1 << 63) - 1).encode(), 1)
+    blob = blob.replace(fc._str("TFORM1", f"{n1}B").encode(), fc._str("TFORM1", f"{(1 << 63) - 1}B").encode(), 1)
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.fits_decrypt(blob, kh, kd)
+    assert e.value.code == gcm.GCM_E_ARG
