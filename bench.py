@@ -239,7 +239,7 @@ def run_decrypt_config4(ctx, gcm, workloads, torch, n_files, side, steps):
     }
 
 
-def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 0.9)):
+def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 0.8, 0.95)):
     """Config 5: Poisson arrivals of 50/50 encrypt / decrypt-verify requests,
     FITS-shaped lognormal sizes (median 4 MiB, 16 KiB..1 GiB, 2880 multiples)
     with a 2880-byte header AAD, keys from a resident 1024-entry table,
@@ -503,25 +503,47 @@ def main():
         ctx.decrypt_verify_async(slot, msg.iv, aad_d, ct_d, tag_d, back_d, ok_d, ws, stream)
         ctx.key_release(slot)
 
+    step_ms = []
+
     def timed(fn, steps, warmup):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
         ctx.profile_read()
         ctx.profile_enable(True)
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        t0.record(stream)
-        for _ in range(steps):
+        # one event between consecutive steps (no synchronisation inside the
+        # timed region): the bracketing pair gives the mean, the rest the spread
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record(stream)
+        for i in range(steps):
             fn()
-        t1.record(stream)
+            ev[i + 1].record(stream)
         torch.cuda.synchronize()
         ctx.profile_enable(False)
         launches, tile_ms = ctx.profile_read()
-        return t0.elapsed_time(t1) / steps, tile_ms / max(1, launches)
+        step_ms[:] = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        return ev[0].elapsed_time(ev[steps]) / steps, tile_ms / max(1, launches)
 
     print("[bench] timing encrypt", file=sys.stderr, flush=True)
     ms_enc, tile_ms = timed(enc_step, args.steps, args.warmup)
+    sv = np.asarray(step_ms)
+    step_stats = {"median": round(float(np.median(sv)), 4), "std": round(float(np.std(sv)), 4),
+                  "p50": round(float(np.percentile(sv, 50)), 4), "p99": round(float(np.percentile(sv, 99)), 4),
+                  "min": round(float(sv.min()), 4), "max": round(float(sv.max()), 4)}
+    # the practical HBM ceiling: a plain device-to-device copy of 1 GiB
+    # (reads 1 GiB, writes 1 GiB), timed the same way
+    ca = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(3)
+    cb = torch.empty_like(ca)
+    for _ in range(2):
+        cb.copy_(ca)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        cb.copy_(ca)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * (1 << 30) / (c0.elapsed_time(c1) / 5 * 1e-3) / 1e9
+    del ca, cb
     print("[bench] timing decrypt-verify", file=sys.stderr, flush=True)
     ms_dec, tile_ms_dec = timed(dec_step, max(1, args.steps // 2), 2)
     accepted = int(ok_d.cpu()[0]) == 1
@@ -621,6 +643,9 @@ def main():
         },
         "hbm_traffic_gbs": round(traffic / (ms_enc * 1e-3) / 1e9, 2),
         "hbm_frac": round(traffic / (ms_enc * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "step_ms": step_stats,
+        "device_copy_traffic_gbs": round(copy_gbs, 1),
+        "hbm_frac_of_device_copy": round(traffic / (ms_enc * 1e-3) / 1e9 / copy_gbs, 4),
         "decrypt_verify_gbs": round(n / (ms_dec * 1e-3) / 1e9, 2),
         "decrypt_accepted_and_round_trip": accepted and same,
         "latency_1mib_aes128_oneshot_ms": {"p50": round(float(np.percentile(lat, 50)), 4),
