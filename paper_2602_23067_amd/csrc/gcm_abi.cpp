@@ -300,9 +300,14 @@ void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t
     constexpr uint64_t kTileCost = 64;
     uint64_t best_cost = ~0ull;
     uint32_t best_l = 16;
-    for (uint32_t l = 16; l >= 8; --l) {
+    for (uint32_t l = 16; l >= 6; --l) {
         const uint64_t B = 1ull << l;
         const uint64_t T = (m + B - 1) / B;
+        // tiles of one or two rows only while every tile gets a wave of its
+        // own: short messages then finish in one row's latency, and long ones
+        // never pay for a partial (and a combine step) per row
+        if (l < 8 && T > R)
+            continue;
         const uint64_t z = T * B - m;
         const uint64_t n0 = (T + R - 1) / R, n1 = T > 1 ? (T - 1 + R - 1) / R : 0;
         const uint64_t c0 = (n0 - 1) * B + (B - z / 64 * 64) + kTileCost * n0;
