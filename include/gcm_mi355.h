@@ -69,7 +69,7 @@ typedef struct gcm_ctx gcm_ctx;
  *     allocate for key slots and scratch (0 = no bound).
  *   key_slots: number of resident key slots (each holds the round keys, H,
  *     the H^(2^k) power table and the GHASH multiplication tables, about
- *     386 KiB; the paper's precomputed table of powers of H).
+ *     387 KiB; the paper's precomputed table of powers of H).
  * Builds the AES tables on the device.  *out receives the context. */
 int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_bytes, uint32_t key_slots);
 

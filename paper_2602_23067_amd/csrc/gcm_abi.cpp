@@ -363,7 +363,7 @@ void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, ui
     d->log2B = log2B;
     d->nr = nr;
     d->groups = (uint32_t)((d->n_tiles + waves - 1) / waves);
-    d->fix_lane = 1;  // callers that mix many keys switch large-table fix-ups off per message
+    d->pad0 = 0;
     d->j0 = 0;
     d->tag_len = 16;
     d->ctr_off = 0;

@@ -114,7 +114,6 @@ extern "C" int gcm_batch_create(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, u
                   (uint64_t)(base_d + j.ok_off), (uint64_t)(ctx->d_slots + kSlotBytes * j.key_slot),
                   ctx->slot_nr[j.key_slot], log2B, waves, tile_base);
         // per-lane fix-up tables only pay off when many work items share the key
-        descs[i].fix_lane = j.len >= kLaneFixMinBytes ? 1u : 0u;
         tile_base += descs[i].n_tiles + 2;  // partials, then the E_K(J0) and J0 slots
         b->total_tiles += descs[i].n_tiles;
         b->any_decrypt |= j.op == 1;

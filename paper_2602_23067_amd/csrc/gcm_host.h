@@ -57,9 +57,6 @@ namespace gcm {
 
 constexpr uint64_t kMaxLen = (1ull << 36) - 32;  // 2^39 - 256 bits
 constexpr uint64_t kMaxAad = (1ull << 61) - 1;   // < 2^64 bits
-// batch/serving messages at least this long use the per-lane fix-up tables
-// (512 KiB per key, shared by the message's many work items)
-constexpr uint64_t kLaneFixMinBytes = 64ull << 20;
 
 int fail(int code, const char *fmt, ...);
 int fail_hip(hipError_t e, const char *what);

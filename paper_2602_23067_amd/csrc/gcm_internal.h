@@ -36,9 +36,9 @@ constexpr uint64_t kTab8Bytes = 16ull * 256 * 16;             // byte-position t
 constexpr uint64_t kTab4Bytes = 32ull * 16 * 16;              // nibble-position table, 8 KiB
 constexpr uint64_t kSlotTab8Off = kSlotHdrBytes;
 constexpr uint64_t kSlotTab4Off = kSlotTab8Off + kTab8Bytes;
-constexpr uint64_t kSlotLaneOff = kSlotTab4Off + kTab4Levels * kTab4Bytes;  // nibble tables of H^e, e = 0..63
-constexpr int kLaneTabs = 64;
-constexpr uint64_t kSlotBytes = kSlotLaneOff + kLaneTabs * kTab4Bytes;
+constexpr uint64_t kSlotLanePowOff = kSlotTab4Off + kTab4Levels * kTab4Bytes;  // H^e, e = 0..63 (tile fix-ups)
+constexpr int kLanePows = 64;
+constexpr uint64_t kSlotBytes = kSlotLanePowOff + kLanePows * 16;
 static_assert(sizeof(KeySlotHdr) <= kSlotHdrBytes, "slot header too large");
 
 // ---- per-message descriptor ----
@@ -68,7 +68,7 @@ struct MsgDesc {
     uint32_t log2B;      // wave tile = 2^log2B blocks (>= 6)
     uint32_t nr;         // AES rounds
     uint32_t groups;     // workgroup items for this message
-    uint32_t fix_lane;   // 1: per-lane fix-up tables H^(63-l); 0: exponent bits over H^(2^k)
+    uint32_t pad0;
     uint64_t j0;         // device address of J0 (16 bytes) for IVs other than 96 bits; 0: J0 = IV || 0^31 || 1
     uint32_t tag_len;    // tag bytes written (encrypt) or compared (decrypt): 16, or 15, 14, 13, 12, 8, 4
     uint32_t ctr_off;    // with j0: data blocks that precede this one (a streamed segment), added to the counters

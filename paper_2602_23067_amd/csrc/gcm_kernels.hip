@@ -447,15 +447,19 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
             const int lvl = b < kTab4Levels ? b : kStrideLevel;
             m_sh = u32x4{hd->hpow[lvl][0], hd->hpow[lvl][1], hd->hpow[lvl][2], hd->hpow[lvl][3]};
         }
-    } else if (tid < 64) {
-        // H^e as the product of H^(2^k) over the set bits of e (one wave)
-        const int e = b - kTab4Levels - 1;
-        u32x4 m = {0x80u, 0u, 0u, 0u};  // the field's one
-        for (int k = 0; k < 6; ++k)
-            if ((e >> k) & 1)
-                m = gf_mul_wave(m, u32x4{hd->hpow[k][0], hd->hpow[k][1], hd->hpow[k][2], hd->hpow[k][3]});
-        if (tid == 0)
-            m_sh = m;
+    } else {
+        // H^e as the product of H^(2^k) over the set bits of e (one wave);
+        // the tile fix-ups multiply by it in registers, so no table is built
+        if (tid < 64) {
+            const int e = b - kTab4Levels - 1;
+            u32x4 m = {0x80u, 0u, 0u, 0u};  // the field's one
+            for (int k = 0; k < 6; ++k)
+                if ((e >> k) & 1)
+                    m = gf_mul_wave(m, u32x4{hd->hpow[k][0], hd->hpow[k][1], hd->hpow[k][2], hd->hpow[k][3]});
+            if (tid == 0)
+                reinterpret_cast<u32x4 *>(slot + kSlotLanePowOff)[e] = m;
+        }
+        return;
     }
     lds_barrier();
     if (tid < 128) {
@@ -476,9 +480,7 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
         }
         return;
     }
-    u32x4 *tab = b < kTab4Levels
-                     ? reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes)
-                     : reinterpret_cast<u32x4 *>(slot + kSlotLaneOff + (uint64_t)(b - kTab4Levels - 1) * kTab4Bytes);
+    u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes);
     for (int e = tid; e < 512; e += 256) {
         const int j = e >> 4, nib = e & 15;
         const int byte = j >> 1, shift = (j & 1) ? 0 : 4;  // even j: high nibble
@@ -508,27 +510,6 @@ __device__ __forceinline__ u32x4 mul_tab4(u32x4 a, const u32x4 *__restrict__ tab
         }
     }
     return r0 ^ r1;
-}
-
-// a * M from a nibble table in global memory, gathers issued sixteen at a time
-__device__ __forceinline__ u32x4 mul_tab4_wide(u32x4 a, const u32x4 *__restrict__ tab)
-{
-    u32x4 r = {0, 0, 0, 0};
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        u32x4 g[16];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int k = 8 * half + q;
-            const uint32_t byte = byte_of(a, k);
-            g[2 * q] = tab[(2 * k) * 16 + (byte >> 4)];
-            g[2 * q + 1] = tab[(2 * k + 1) * 16 + (byte & 15)];
-        }
-#pragma unroll
-        for (int q = 0; q < 16; q += 2)
-            r = xor3v(r, g[q], g[q + 1]);
-    }
-    return r;
 }
 
 __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
@@ -817,6 +798,35 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
     }
 }
 
+// a * c for a per-lane c in VALU only (a comb over the 32 bit positions of
+// the words of a: 256-bit accumulate with word-aligned XORs, one fold at the
+// end), about 950 VALU instructions and no memory traffic
+__device__ __forceinline__ u32x4 gf_mul_comb(u32x4 a, u32x4 c)
+{
+    const uint32_t am[4] = {a.x, a.y, a.z, a.w}, cm[4] = {c.x, c.y, c.z, c.w};
+    const P128 pa = mem_to_poly(am), pc = mem_to_poly(cm);
+    const uint32_t aw[4] = {(uint32_t)pa.lo, (uint32_t)(pa.lo >> 32), (uint32_t)pa.hi, (uint32_t)(pa.hi >> 32)};
+    const uint32_t cw[4] = {(uint32_t)pc.lo, (uint32_t)(pc.lo >> 32), (uint32_t)pc.hi, (uint32_t)(pc.hi >> 32)};
+    uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int b = 31; b >= 0; --b) {
+#pragma unroll
+        for (int k = 7; k > 0; --k)
+            acc[k] = __builtin_amdgcn_alignbit(acc[k], acc[k - 1], 31);  // acc <<= 1
+        acc[0] <<= 1;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const uint32_t m = 0u - ((aw[w] >> b) & 1u);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[w + j] ^= cw[j] & m;
+        }
+    }
+    const P128 r = poly_reduce((uint64_t)acc[0] | ((uint64_t)acc[1] << 32), (uint64_t)acc[2] | ((uint64_t)acc[3] << 32),
+                               (uint64_t)acc[4] | ((uint64_t)acc[5] << 32), (uint64_t)acc[6] | ((uint64_t)acc[7] << 32));
+    return poly_to_mem(r);
+}
+
 // One wave processes wave tile t of message d: rows of 64 consecutive
 // blocks, lane l on block 64*r + l, so every load/store instruction moves one
 // contiguous KiB.  a_l = sum_r X_(64r+l) * (H^64)^(R-1-r) by Horner; then
@@ -968,21 +978,10 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     if (!GH)
         return;
 
-    // fix-up: a * H^(63 - lane).  Messages whose key tables are shared by many
-    // tiles use one multiply with that lane's table; others walk the exponent
-    // bits through the six H^(2^k) tables (48 KiB instead of 512 KiB per key).
-    if (d.fix_lane) {
-        a = mul_tab4_wide(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLaneOff) + (uint64_t)(63 - lane) * 512);
-    } else {
-        const uint32_t e = 63u - (uint32_t)lane;
-        const u32x4 *lv = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab4Off);
-#pragma unroll 1
-        for (int k = 0; k < 6; ++k) {
-            const u32x4 m = mul_tab4_wide(a, lv + (uint64_t)k * 512);
-            if ((e >> k) & 1)
-                a = m;
-        }
-    }
+    // fix-up: a * H^(63 - lane), multiplied in registers (the powers sit in
+    // one contiguous KiB of the key slot, so this is one coalesced load and no
+    // table gathers at the end of the tile)
+    a = gf_mul_comb(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLanePowOff)[63 - lane]);
     a = wave_xor_reduce(a);
     if (lane == 0)
         partials[d.tile_base + t] = a;
@@ -1308,7 +1307,7 @@ hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLaneTabs, m), dim3(256), 0, s, sc);
+        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLanePows, m), dim3(256), 0, s, sc);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -133,7 +133,6 @@ static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &ba
         fill_desc(&descs[i], r.op, r.iv, (uint64_t)r.aad_d, r.aad_len, (uint64_t)r.in_d, (uint64_t)r.out_d, r.len,
                   (uint64_t)r.tag_d, 0, (uint64_t)(ctx->d_slots + kSlotBytes * r.key_slot), ctx->slot_nr[r.key_slot],
                   l, waves, tile_base);
-        descs[i].fix_lane = r.len >= kLaneFixMinBytes ? 1u : 0u;
         tile_base += descs[i].n_tiles + 2;  // partials, then the E_K(J0) and J0 slots
         n_tiles += descs[i].n_tiles;
         n_items += descs[i].groups;

@@ -87,7 +87,6 @@ static void segment_desc(const gcm_stream *st, MsgDesc *d)
     fill_desc(d, st->op, zero_iv, 0, 0, 0, 0, 0, 0, 0, (uint64_t)(st->ctx->d_slots + kSlotBytes * st->slot), st->nr,
               6, 16, 0);
     d->j0 = (uint64_t)(st->d_state + 16);
-    d->fix_lane = 1;
 }
 
 extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
