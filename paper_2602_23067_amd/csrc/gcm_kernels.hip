@@ -1091,19 +1091,22 @@ constexpr int kCombineThreads = 1024;
 constexpr int kCombineLog2 = 10;
 
 // S = sum_t p_t * H^((T-1-t)*B + 1); tag = S xor E_K(J0).  Thread i runs a
-// Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B),
-// lifts its value by H^((T-1-t_last)*B) through the exponent bits, and the
-// XOR over threads closes the tree; one more *H accounts for GHASH's final
-// multiplication.  The nibble tables this needs (at most 12 of 8 KiB) are
-// staged in LDS first, so every multiply is 32 LDS reads.  E_K(J0) was left
-// by the tile kernel right after the message's T partials.
+// Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B);
+// its value then needs the weight H^((T-1-t_last)*B), and with N = 2^k >=
+// min(T, 1024) leaves and r = T mod N that weight is H^((N-1-j)*B) for leaf
+// j = (i - r) mod N.  A binary tree over the leaves, L*H^(B*2^lev) ^ R at
+// level lev, closes the sum in k levels with N - 1 products in all; one more
+// *H accounts for GHASH's final multiplication.  The nibble tables this needs
+// (at most 12 of 8 KiB) are staged in LDS first, so every multiply is 32 LDS
+// reads.  E_K(J0) was left by the tile kernel right after the message's T
+// partials.
 template <bool BATCH>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
 {
     __shared__ u32x4 tabs[kCombineLog2 + 2][512];  // [0]: H; [1+k]: H^(B*2^k), k = 0..10
-    __shared__ u32x4 red[kCombineThreads / 64];
+    __shared__ u32x4 leaf[kCombineThreads];
     const MsgDesc d = BATCH ? load_const<MsgDesc>(descs + blockIdx.x) : single;
     const uint32_t i = threadIdx.x;
     const uint64_t T = d.n_tiles;
@@ -1148,7 +1151,6 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
 
     u32x4 acc = {0, 0, 0, 0};
     if (i < T) {
-        uint64_t t_last = i;
         for (uint64_t t0 = i; t0 < T; t0 += 8 * (uint64_t)kCombineThreads) {
             if (t0 != i) {
 #pragma unroll
@@ -1160,28 +1162,27 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 const uint64_t t = t0 + (uint64_t)q * kCombineThreads;
-                if (t < T) {
+                if (t < T)
                     acc = (horner ? mul_tab4(acc, tabs[1 + kCombineLog2]) : acc) ^ pv[q];
-                    t_last = t;
-                }
             }
         }
-        const uint64_t e = T - 1 - t_last;
-        for (int k = 0; k < nbits; ++k) {
-            const u32x4 m = mul_tab4(acc, tabs[1 + k]);
-            if ((e >> k) & 1)
-                acc = m;
-        }
     }
-    acc = wave_xor_reduce(acc);
-    if ((i & 63) == 0)
-        red[i >> 6] = acc;
+    // leaves: thread i (< N) at (i - r) mod N; threads without partials hold 0
+    const uint32_t N = 1u << nbits;
+    const uint32_t r = (uint32_t)(T & (uint64_t)(N - 1));
+    if (i < N)
+        leaf[(i - r) & (N - 1)] = acc;
     lds_barrier();
+    for (int lev = 0; lev < nbits; ++lev) {
+        const uint32_t pairs = N >> (lev + 1);
+        if (i < pairs) {
+            const uint32_t a = (2 * i) << lev, b = a + (1u << lev);
+            leaf[a] = mul_tab4(leaf[a], tabs[1 + lev]) ^ leaf[b];
+        }
+        lds_barrier();
+    }
     if (i == 0) {
-        u32x4 s = red[0];
-        for (int w = 1; w < kCombineThreads / 64; ++w)
-            s ^= red[w];
-        s = mul_tab4(s, tabs[0]);  // * H
+        const u32x4 s = mul_tab4(leaf[0], tabs[0]);  // * H
         if (d.yout) {  // a streamed segment: hand on its GHASH value
             *reinterpret_cast<u32x4 *>(d.yout) = s;
             return;
