@@ -32,7 +32,7 @@ LDS_PEAK_TBS = 128 * 256 * 2.4e9 / 1e12  # LDS bytes per clock per CU x CUs x cl
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--ny", type=int, default=16384)
     ap.add_argument("--nx", type=int, default=16384)
@@ -371,7 +371,7 @@ def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag
             return st  # kept alive (and its state allocated) until after the timed region
 
         live = []
-        ms_stream, _ = timed(lambda: live.append(streamed()), max(2, args.steps // 2), 1)
+        ms_stream, _ = timed(lambda: live.append(streamed()), max(2, min(10, args.steps // 2)), 1)
         torch.cuda.synchronize()
         for st in live:
             st.close()
@@ -607,7 +607,7 @@ def main():
         print("[bench] config 3 batch", file=sys.stderr, flush=True)
         del pt_d, ct_d, back_d
         torch.cuda.empty_cache()
-        batch3 = run_batch_config3(ctx, gcm, workloads, torch, args.batch_msgs, max(1, args.steps // 4))
+        batch3 = run_batch_config3(ctx, gcm, workloads, torch, args.batch_msgs, max(1, min(20, args.steps // 4)))
     dec4 = None
     if not args.skip_dec_batch:
         print("[bench] config 4 decrypt batch", file=sys.stderr, flush=True)
