@@ -45,14 +45,6 @@ static const uint8_t kZeroIv[12] = {0};
 
 // ---------------------------------------------------------------- context
 
-static uint32_t ceil_log2(uint64_t x)
-{
-    uint32_t l = 0;
-    while ((1ull << l) < x)
-        ++l;
-    return l;
-}
-
 int gcm::ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes)
 {
     if (ctx->budget && ctx->used + bytes > ctx->budget)

@@ -307,7 +307,8 @@ bool valid_structure(const Structure &s)
 {
     const long long b = s.bitpix;
     const bool bp = b == 8 || b == 16 || b == 32 || b == 64 || b == -32 || b == -64;
-    if (!bp || s.naxis != 2 || s.naxis1 < 0 || s.naxis2 < 0 || s.naxis1 > kMaxLen || s.naxis2 > kMaxLen)
+    if (!bp || s.naxis != 2 || s.naxis1 < 0 || s.naxis2 < 0 || (uint64_t)s.naxis1 > kMaxLen ||
+        (uint64_t)s.naxis2 > kMaxLen)
         return false;
     const unsigned __int128 n = (unsigned __int128)(uint64_t)((b < 0 ? -b : b) / 8) * (uint64_t)s.naxis1 *
                                 (uint64_t)s.naxis2;
