@@ -82,6 +82,15 @@ def lib() -> ctypes.CDLL:
         L.oracle_gcm_hash.argtypes = [u8p, u8p, u64, u8p, u64, u8p]
         L.oracle_gctr.argtypes = [u8p, sz, u8p, u8p, u64, u8p]
         L.oracle_gctr.restype = ctypes.c_int
+        L.oracle_gcm_siv_encrypt.argtypes = [u8p, sz, u8p, sz, u8p, u64, u8p, u64, u8p, u8p]
+        L.oracle_gcm_siv_encrypt.restype = ctypes.c_int
+        L.oracle_gcm_siv_decrypt_verify.argtypes = [u8p, sz, u8p, sz, u8p, u64, u8p, u64, u8p, u8p,
+                                                    ctypes.POINTER(ctypes.c_int)]
+        L.oracle_gcm_siv_decrypt_verify.restype = ctypes.c_int
+        L.oracle_gcm_siv_derive.argtypes = [u8p, sz, u8p, u8p, u8p]
+        L.oracle_gcm_siv_derive.restype = ctypes.c_int
+        L.oracle_polyval.argtypes = [u8p, u8p, u64, u8p]
+        L.oracle_pv_mul.argtypes = [u8p, u8p, u8p]
         _lib = L
     return _lib
 
@@ -291,3 +300,57 @@ def gctr(key: bytes, icb: bytes, data) -> np.ndarray:
     if rc:
         raise OracleError(rc)
     return out
+
+
+# ---------------------------------------------------------------- AES-GCM-SIV (RFC 8452)
+
+def polyval(h: bytes, data) -> bytes:
+    """POLYVAL(H, X_1..X_s) over whole 16-byte blocks."""
+    d = _buf(data)
+    assert d.size % 16 == 0
+    out = ctypes.create_string_buffer(16)
+    lib().oracle_polyval(bytes(h), _ptr(d), d.size // 16, out)
+    return out.raw
+
+
+def pv_mul(a: bytes, b: bytes) -> bytes:
+    """a * b mod x^128 + x^127 + x^126 + x^121 + 1 (POLYVAL's field, no x^-128)."""
+    out = ctypes.create_string_buffer(16)
+    lib().oracle_pv_mul(bytes(a), bytes(b), out)
+    return out.raw
+
+
+def gcm_siv_derive(kgk: bytes, nonce: bytes):
+    """(message authentication key, message encryption key) for this nonce."""
+    auth = ctypes.create_string_buffer(16)
+    enc = ctypes.create_string_buffer(32)
+    rc = lib().oracle_gcm_siv_derive(bytes(kgk), len(kgk), bytes(nonce), auth, enc)
+    if rc:
+        raise OracleError(rc)
+    return auth.raw, enc.raw[:len(kgk)]
+
+
+def gcm_siv_encrypt(kgk: bytes, nonce: bytes, aad, pt, out: Optional[np.ndarray] = None):
+    """Returns (ciphertext as np.uint8 array, 16-byte tag)."""
+    a = _buf(aad)
+    p = _buf(pt)
+    ct = out if out is not None else np.empty(p.size, dtype=np.uint8)
+    tag = ctypes.create_string_buffer(16)
+    rc = lib().oracle_gcm_siv_encrypt(bytes(kgk), len(kgk), bytes(nonce), len(nonce), _ptr(a), a.size,
+                                      _ptr(p), p.size, _ptr(ct), tag)
+    if rc:
+        raise OracleError(rc)
+    return ct, tag.raw
+
+
+def gcm_siv_decrypt_verify(kgk: bytes, nonce: bytes, aad, ct, tag: bytes, out: Optional[np.ndarray] = None):
+    """Returns (plaintext or zeros as np.uint8 array, accept flag)."""
+    a = _buf(aad)
+    c = _buf(ct)
+    pt = out if out is not None else np.empty(c.size, dtype=np.uint8)
+    acc = ctypes.c_int(-1)
+    rc = lib().oracle_gcm_siv_decrypt_verify(bytes(kgk), len(kgk), bytes(nonce), len(nonce), _ptr(a), a.size,
+                                             _ptr(c), c.size, bytes(tag), _ptr(pt), ctypes.byref(acc))
+    if rc:
+        raise OracleError(rc)
+    return pt, bool(acc.value)

@@ -20,6 +20,11 @@
  *                 for 96 bits, else GHASH of the padded IV and its length,
  *                 sec. 7.1 step 2); tags of t = 128, 120, 112, 104, 96, 64
  *                 or 32 bits (sec. 5.2.1.2), T = MSB_t of the full tag.
+ *   AES-GCM-SIV -- RFC 8452 sec. 3-5 (the misuse-resistant alternative the
+ *                 paper names under future directions): POLYVAL from its own
+ *                 field definition, per-nonce key derivation, tag, and the
+ *                 little-endian 32-bit counter; 16- or 32-byte keys, 12-byte
+ *                 nonces.
  *
  * Readings where the paper is silent (listed in full in the design notes):
  *   - key sizes 16/24/32 bytes accepted (the paper uses AES-128 only);
@@ -35,7 +40,11 @@
  * GF(2^128) product on all 128x128 basis pairs against an independent
  * polynomial formulation, field axioms, Horner == closed form == every tree
  * bracketing, full GCM equality with OpenSSL's EVP AES-GCM, round trip and
- * single-bit-flip rejection.
+ * single-bit-flip rejection; for GCM-SIV (tests/test_oracle_siv_pins.py):
+ * POLYVAL's product against an integer formulation and closed forms,
+ * POLYVAL against OpenSSL's GHASH through RFC 8452 appendix A's byte
+ * reversal identity, derivation / tag / counter keystream (including a
+ * counter wrap) against OpenSSL's AES-ECB, and the AEAD properties.
  */
 #include <stdint.h>
 #include <stddef.h>
@@ -586,3 +595,234 @@ int oracle_gctr(const uint8_t *key, size_t key_len, const uint8_t icb[16], const
     gctr(w, nr, icb, x, len, y);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------ */
+/* AES-GCM-SIV (RFC 8452), the nonce-misuse-resistant AEAD the paper   */
+/* names as an alternative (Discussion and Future Work, "Future        */
+/* Directions", item 4).                                               */
+/*                                                                     */
+/* POLYVAL (RFC 8452 sec. 3): blocks are little-endian polynomials --  */
+/* byte k bit j (value 1<<j) is the coefficient of x^(8k+j) -- in      */
+/* GF(2)[x] / P, P = x^128 + x^127 + x^126 + x^121 + 1;                */
+/* dot(a, b) = a * b * x^-128; S_0 = 0, S_j = dot(S_(j-1) ^ X_j, H).   */
+/* ------------------------------------------------------------------ */
+
+/* v * x mod P: shift towards byte 15; the x^128 carry folds back as   */
+/* x^127 + x^126 + x^121 + 1                                           */
+static void pv_mul_x(uint8_t v[16])
+{
+    int carry = v[15] >> 7;
+    for (int k = 15; k > 0; k--)
+        v[k] = (uint8_t)((v[k] << 1) | (v[k - 1] >> 7));
+    v[0] = (uint8_t)(v[0] << 1);
+    if (carry) {
+        v[0] ^= 0x01;
+        v[15] ^= 0xC2;
+    }
+}
+
+/* v * x^-1 mod P: if the x^0 coefficient is set, add P first (making  */
+/* v divisible by x), then shift towards byte 0; P / x contributes     */
+/* x^127 + x^126 + x^125 + x^120                                       */
+static void pv_mul_xinv(uint8_t v[16])
+{
+    int low = v[0] & 1;
+    for (int k = 0; k < 15; k++)
+        v[k] = (uint8_t)((v[k] >> 1) | (v[k + 1] << 7));
+    v[15] >>= 1;
+    if (low)
+        v[15] ^= 0xE1;
+}
+
+/* a * b mod P, shift-and-add over the bits of a */
+static void pv_mul(const uint8_t a[16], const uint8_t b[16], uint8_t out[16])
+{
+    uint8_t z[16] = {0}, v[16];
+    memcpy(v, b, 16);
+    for (int i = 0; i < 128; i++) {
+        if ((a[i / 8] >> (i % 8)) & 1)
+            for (int k = 0; k < 16; k++)
+                z[k] ^= v[k];
+        pv_mul_x(v);
+    }
+    memcpy(out, z, 16);
+}
+
+static void pv_dot(const uint8_t a[16], const uint8_t b[16], uint8_t out[16])
+{
+    uint8_t t[16];
+    pv_mul(a, b, t);
+    for (int i = 0; i < 128; i++)
+        pv_mul_xinv(t);
+    memcpy(out, t, 16);
+}
+
+static void polyval_absorb_block(uint8_t s[16], const uint8_t h[16], const uint8_t x[16])
+{
+    uint8_t t[16];
+    for (int k = 0; k < 16; k++)
+        t[k] = s[k] ^ x[k];
+    pv_dot(t, h, s);
+}
+
+static void polyval_absorb_padded(uint8_t s[16], const uint8_t h[16], const uint8_t *data, uint64_t len)
+{
+    uint64_t off = 0;
+    while (off < len) {
+        uint8_t blk[16] = {0};
+        uint64_t take = len - off < 16 ? len - off : 16;
+        memcpy(blk, data + off, (size_t)take);
+        polyval_absorb_block(s, h, blk);
+        off += take;
+    }
+}
+
+static void put_le64(uint8_t *p, uint64_t v)
+{
+    for (int k = 0; k < 8; k++)
+        p[k] = (uint8_t)(v >> (8 * k));
+}
+
+/* RFC 8452 sec. 6: P_MAX = A_MAX = 2^36 bytes */
+#define ORACLE_SIV_MAX ((((uint64_t)1) << 36))
+
+/* sec. 4: message_authentication_key = first halves of AES_KGK(LE32(0)||N),
+ * AES_KGK(LE32(1)||N); message_encryption_key = those of LE32(2), LE32(3)
+ * (and LE32(4), LE32(5) for a 256-bit key-generating key) */
+static int siv_derive(const uint8_t *kgk, size_t kgk_len, const uint8_t nonce[12], uint8_t auth[16], uint8_t *enc)
+{
+    if (kgk_len != 16 && kgk_len != 32)
+        return ORACLE_E_KEYLEN;
+    uint8_t w[AES_MAX_WORDS][4];
+    int nr = key_expansion(kgk, kgk_len, w);
+    int nblk = kgk_len == 16 ? 4 : 6;
+    for (int i = 0; i < nblk; i++) {
+        uint8_t in[16], out[16];
+        put_le64(in, (uint64_t)i); /* LE32(i); bytes 4..7 are overwritten by the nonce */
+        memcpy(in + 4, nonce, 12);
+        aes_cipher(w, nr, in, out);
+        memcpy(i < 2 ? auth + 8 * i : enc + 8 * (i - 2), out, 8);
+    }
+    return ORACLE_OK;
+}
+
+/* S_s = POLYVAL(auth, pad(A) || pad(P) || LE64(8|A|) || LE64(8|P|)), then
+ * the nonce XORed into bytes 0..11 and the top bit of byte 15 cleared;
+ * tag = AES_enc(S_s) */
+static void siv_tag(const uint8_t auth[16], uint8_t we[AES_MAX_WORDS][4], int nre, const uint8_t nonce[12],
+                    const uint8_t *aad, uint64_t aad_len, const uint8_t *pt, uint64_t len, uint8_t tag[16])
+{
+    uint8_t s[16] = {0}, lb[16];
+    polyval_absorb_padded(s, auth, aad, aad_len);
+    polyval_absorb_padded(s, auth, pt, len);
+    put_le64(lb, aad_len * 8);
+    put_le64(lb + 8, len * 8);
+    polyval_absorb_block(s, auth, lb);
+    for (int k = 0; k < 12; k++)
+        s[k] ^= nonce[k];
+    s[15] &= 0x7F;
+    aes_cipher(we, nre, s, tag);
+}
+
+/* counter block = tag with the top bit of byte 15 set; bytes 0..3 are a
+ * little-endian 32-bit counter incremented mod 2^32 per block */
+static void siv_ctr(uint8_t we[AES_MAX_WORDS][4], int nre, const uint8_t tag[16], const uint8_t *x, uint64_t len,
+                    uint8_t *y)
+{
+    uint8_t cb[16];
+    memcpy(cb, tag, 16);
+    cb[15] |= 0x80;
+    uint64_t off = 0;
+    while (off < len) {
+        uint8_t ks[16];
+        aes_cipher(we, nre, cb, ks);
+        uint64_t take = len - off < 16 ? len - off : 16;
+        for (uint64_t k = 0; k < take; k++)
+            y[off + k] = x[off + k] ^ ks[k];
+        uint32_t c = (uint32_t)cb[0] | ((uint32_t)cb[1] << 8) | ((uint32_t)cb[2] << 16) | ((uint32_t)cb[3] << 24);
+        c += 1;
+        cb[0] = (uint8_t)c;
+        cb[1] = (uint8_t)(c >> 8);
+        cb[2] = (uint8_t)(c >> 16);
+        cb[3] = (uint8_t)(c >> 24);
+        off += take;
+    }
+}
+
+static int siv_setup(const uint8_t *kgk, size_t kgk_len, const uint8_t *nonce, size_t nonce_len, uint64_t aad_len,
+                     uint64_t len, uint8_t auth[16], uint8_t we[AES_MAX_WORDS][4], int *nre)
+{
+    if (!kgk || !nonce)
+        return ORACLE_E_ARG;
+    if (kgk_len != 16 && kgk_len != 32)
+        return ORACLE_E_KEYLEN;
+    if (nonce_len != 12)
+        return ORACLE_E_IVLEN;
+    if (len > ORACLE_SIV_MAX || aad_len > ORACLE_SIV_MAX)
+        return ORACLE_E_TOOLONG;
+    uint8_t enc[32];
+    siv_derive(kgk, kgk_len, nonce, auth, enc);
+    *nre = key_expansion(enc, kgk_len, we);
+    return ORACLE_OK;
+}
+
+int oracle_gcm_siv_encrypt(const uint8_t *kgk, size_t kgk_len, const uint8_t *nonce, size_t nonce_len,
+                           const uint8_t *aad, uint64_t aad_len, const uint8_t *pt, uint64_t len, uint8_t *ct,
+                           uint8_t tag[16])
+{
+    uint8_t auth[16], we[AES_MAX_WORDS][4];
+    int nre;
+    int rc = siv_setup(kgk, kgk_len, nonce, nonce_len, aad_len, len, auth, we, &nre);
+    if (rc)
+        return rc;
+    if ((len && (!pt || !ct)) || (aad_len && !aad) || !tag)
+        return ORACLE_E_ARG;
+    siv_tag(auth, we, nre, nonce, aad, aad_len, pt, len, tag);
+    siv_ctr(we, nre, tag, pt, len, ct);
+    return ORACLE_OK;
+}
+
+/* decrypt with the counter taken from the received tag, recompute the tag
+ * over the recovered plaintext, compare all 16 bytes; on mismatch the
+ * plaintext output is zero-filled and *accept is 0 */
+int oracle_gcm_siv_decrypt_verify(const uint8_t *kgk, size_t kgk_len, const uint8_t *nonce, size_t nonce_len,
+                                  const uint8_t *aad, uint64_t aad_len, const uint8_t *ct, uint64_t len,
+                                  const uint8_t tag[16], uint8_t *pt, int *accept)
+{
+    uint8_t auth[16], we[AES_MAX_WORDS][4];
+    int nre;
+    int rc = siv_setup(kgk, kgk_len, nonce, nonce_len, aad_len, len, auth, we, &nre);
+    if (rc)
+        return rc;
+    if ((len && (!pt || !ct)) || (aad_len && !aad) || !tag || !accept)
+        return ORACLE_E_ARG;
+    siv_ctr(we, nre, tag, ct, len, pt);
+    uint8_t want[16];
+    siv_tag(auth, we, nre, nonce, aad, aad_len, pt, len, want);
+    uint8_t diff = 0;
+    for (int k = 0; k < 16; k++)
+        diff |= (uint8_t)(want[k] ^ tag[k]);
+    *accept = diff == 0;
+    if (!*accept && len)
+        memset(pt, 0, (size_t)len);
+    return ORACLE_OK;
+}
+
+/* the derived per-nonce keys (enc gets kgk_len bytes) */
+int oracle_gcm_siv_derive(const uint8_t *kgk, size_t kgk_len, const uint8_t nonce[12], uint8_t auth[16],
+                          uint8_t *enc)
+{
+    if (!kgk || !nonce || !auth || !enc)
+        return ORACLE_E_ARG;
+    return siv_derive(kgk, kgk_len, nonce, auth, enc);
+}
+
+void oracle_polyval(const uint8_t h[16], const uint8_t *x, uint64_t nblocks, uint8_t out[16])
+{
+    uint8_t s[16] = {0};
+    for (uint64_t i = 0; i < nblocks; i++)
+        polyval_absorb_block(s, h, x + 16 * i);
+    memcpy(out, s, 16);
+}
+
+void oracle_pv_mul(const uint8_t a[16], const uint8_t b[16], uint8_t out[16]) { pv_mul(a, b, out); }
