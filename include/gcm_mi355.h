@@ -293,6 +293,45 @@ void gcm_fits_free(gcm_fits_result *r);
 /* 12 bytes from the kernel's entropy pool (getrandom), for NONCE_H / NONCE_D. */
 int gcm_fits_nonce(uint8_t out[12]);
 
+/* ---------------------------------------------------------------- AES-GCM-SIV */
+
+/* AES-GCM-SIV (RFC 8452): the nonce-misuse-resistant AEAD that the paper
+ * names as the alternative to GCM where several operators may share a key
+ * (Discussion and Future Work, "Future Directions", item 4).  A repeated
+ * nonce then reveals only whether two messages are equal.
+ *
+ * The key-generating key is a registered slot of 16 or 32 bytes (24 is
+ * GCM_E_KEYLEN); nonces are 12 bytes (else GCM_E_IVLEN); AAD and data are at
+ * most 2^36 bytes each (else GCM_E_TOOLONG).  Per message the device derives
+ * the authentication and encryption keys from the nonce, computes the tag
+ * over POLYVAL(AAD, data) and encrypts in counter mode from the tag, so
+ * encryption reads the plaintext twice; decryption is one fused pass.
+ * Buffers: device memory, data and AAD 16-byte aligned, input and output
+ * identical or disjoint; the tag may sit anywhere in device memory.
+ *
+ * Device scratch for a message of `len` data and `aad_len` AAD bytes: a key
+ * slot for the derived keys (about 387 KiB), the POLYVAL value and counter
+ * block, and the per-tile partial hashes.  A workspace may be reused by calls
+ * that are ordered on one stream. */
+uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
+
+/* Encrypt: ct_d = the ciphertext, tag_d (device, 16 bytes) = the tag, both
+ * written by kernels on `stream`; workspace_d: at least
+ * gcm_siv_workspace_size() bytes, 256-byte aligned.  The call returns once
+ * the kernels are enqueued. */
+int gcm_siv_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *nonce, size_t nonce_len,
+                          const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
+                          uint8_t *tag_d, void *workspace_d, uint64_t workspace_bytes, void *stream);
+
+/* Decrypt-verify: counter mode from the received tag (device, 16 bytes),
+ * the tag recomputed over the recovered plaintext and compared in all 16
+ * bytes; accept_d (device int32) = 1 accept, 0 reject, and on reject pt_d is
+ * zero-filled by a later kernel on the same stream. */
+int gcm_siv_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *nonce, size_t nonce_len,
+                                 const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
+                                 const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
+                                 uint64_t workspace_bytes, void *stream);
+
 /* ---------------------------------------------------------------- batches */
 
 /* One message of a batch.  All offsets are byte offsets into one device

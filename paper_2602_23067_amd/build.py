@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgcm_mi355.so")
 
-SOURCES = ["gcm_kernels.hip", "gcm_abi.cpp", "gcm_batch.cpp", "gcm_serve.cpp", "gcm_autotune.cpp", "gcm_pipeline.cpp", "gcm_stream.cpp", "gcm_fits.cpp"]
+SOURCES = ["gcm_kernels.hip", "gcm_abi.cpp", "gcm_batch.cpp", "gcm_serve.cpp", "gcm_autotune.cpp", "gcm_pipeline.cpp", "gcm_stream.cpp", "gcm_fits.cpp",
+           "gcm_siv.cpp"]
 
 FLAGS = [
     "--offload-arch=gfx950",

@@ -395,6 +395,11 @@ int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const 
     if (len > kMaxLen || aad_len > kMaxAad)
         return fail(GCM_E_TOOLONG, "len %llu / aad_len %llu beyond the SP 800-38D limits",
                     (unsigned long long)len, (unsigned long long)aad_len);
+    return check_buffers(aad_len, len, aad_d, in_d, out_d);
+}
+
+int gcm::check_buffers(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
+{
     if ((len && (!in_d || !out_d)) || (aad_len && !aad_d))
         return fail(GCM_E_ARG, "NULL device buffer with non-zero length");
     const uintptr_t a = (uintptr_t)aad_d, i = (uintptr_t)in_d, o = (uintptr_t)out_d;

@@ -76,6 +76,8 @@ void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_
                uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr, uint32_t log2B,
                uint32_t waves, uint64_t tile_base);
 int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
+// NULL, alignment (16 B) and partial-overlap checks of device buffers
+int check_buffers(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
 uint64_t workspace_counter_bytes(uint64_t n_msgs);
 uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
 // IV lengths the device path takes (1..kMaxIvBytes bytes)
@@ -111,5 +113,17 @@ hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *
 hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);
+// AES-GCM-SIV: message keys into the slot at out_slot (and, with tag_in, the
+// counter block from the received tag at ctr_out); the tile passes (0 POLYVAL
+// only, 1 counter mode only, 2 counter mode + POLYVAL of the output); the tag
+// from the POLYVAL value at g (encrypt: tag_out and the counter block;
+// decrypt: compare with tag_in, accept flag and reject count)
+hipError_t launch_siv_derive(uint64_t kgk_slot, const uint8_t nonce[12], uint64_t out_slot, const uint8_t *tag_in,
+                             void *ctr_out, const uint32_t *te0, const uint32_t *sbox, const void *frob, hipStream_t s);
+hipError_t launch_siv_tiles(int waves, int pass, const MsgDesc &d, uint32_t n_items, const uint32_t *te0,
+                            void *partials, uint32_t grid, hipStream_t s);
+hipError_t launch_siv_tag(uint64_t slot, const void *g, const uint8_t nonce[12], uint8_t *tag_out, void *ctr_out,
+                          const uint8_t *tag_in, int32_t *ok, uint32_t *counters, const uint32_t *te0,
+                          const uint32_t *sbox, hipStream_t s);
 
 }  // namespace gcm

@@ -313,16 +313,14 @@ __global__ __launch_bounds__(256) void k_frob_tables(u32x4 *frob)
 }
 
 // FIPS-197 key expansion with the key length fixed at compile time (fully
-// unrolled, so the schedule stays in registers), then H = E_K(0^128).
+// unrolled, so the schedule stays in registers) into w and the slot header.
 template <int NK>
-__device__ __forceinline__ void expand_and_hash(const KeyArg &key, KeySlotHdr *hd, const uint32_t *te0,
-                                                const uint32_t *sb, uint32_t h[4])
+__device__ __forceinline__ void expand_key(const uint32_t *kw, KeySlotHdr *hd, const uint32_t *sb, uint32_t *w)
 {
     constexpr int NR = NK + 6, NW = 4 * (NR + 1);
-    uint32_t w[NW];
 #pragma unroll
     for (int i = 0; i < NK; ++i)
-        w[i] = key.w[i];
+        w[i] = kw[i];
     uint32_t rcon = 1;
 #pragma unroll
     for (int i = NK; i < NW; ++i) {
@@ -340,8 +338,57 @@ __device__ __forceinline__ void expand_and_hash(const KeyArg &key, KeySlotHdr *h
         hd->rk[i] = i < NW ? w[i] : 0u;
     hd->nr = (uint32_t)NR;
     hd->key_len = (uint32_t)(4 * NK);
+}
+
+// key expansion, then H = E_K(0^128)
+template <int NK>
+__device__ __forceinline__ void expand_and_hash(const KeyArg &key, KeySlotHdr *hd, const uint32_t *te0,
+                                                const uint32_t *sb, uint32_t h[4])
+{
+    constexpr int NR = NK + 6;
+    uint32_t w[4 * (NR + 1)];
+    expand_key<NK>(key.w, hd, sb, w);
     const uint32_t zero[4] = {0, 0, 0, 0};
     aes_block<NR>(w, te0, sb, zero, h);
+}
+
+// Lane k < kPowLevels of the calling wave writes H^(2^k) = F_k(H) to the
+// slot header (F_0 is the identity).
+__device__ __forceinline__ void write_hpow(KeySlotHdr *hd, const uint32_t *h, const u32x4 *__restrict__ frob)
+{
+    const int k = threadIdx.x;
+    if (k < kPowLevels) {
+        const u32x4 H = u32x4{h[0], h[1], h[2], h[3]};
+        u32x4 r = H;
+        if (k > 0) {
+            const u32x4 *F = frob + (uint64_t)(k - 1) * 4096;
+            r = u32x4{0, 0, 0, 0};
+            for (int j = 0; j < 16; ++j)
+                r ^= F[j * 256 + byte_of(H, j)];
+        }
+        hd->hpow[k][0] = r.x;
+        hd->hpow[k][1] = r.y;
+        hd->hpow[k][2] = r.z;
+        hd->hpow[k][3] = r.w;
+    }
+}
+
+// AES tables (TE0 and the S-box as words) from global memory into LDS,
+// by one 64-thread workgroup; the caller adds the barrier.
+__device__ __forceinline__ void stage_aes_tables64(uint32_t *te0, uint32_t *sb, const uint32_t *te0g,
+                                                   const uint32_t *sbg)
+{
+    uint32_t a[4], b[4];  // all eight loads in flight before the stores
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        a[r] = te0g[threadIdx.x + 64 * r];
+        b[r] = sbg[threadIdx.x + 64 * r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        te0[threadIdx.x + 64 * r] = a[r];
+        sb[threadIdx.x + 64 * r] = b[r];
+    }
 }
 
 // One workgroup per key (blockIdx.x indexes `keys`/`slots`): the AES tables
@@ -352,19 +399,7 @@ __global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t
 {
     __shared__ uint32_t te0[256], sb[256];
     __shared__ uint32_t h_sh[4];
-    {
-        uint32_t a[4], b[4];  // all eight loads in flight before the stores
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            a[r] = te0g[threadIdx.x + 64 * r];
-            b[r] = sbg[threadIdx.x + 64 * r];
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            te0[threadIdx.x + 64 * r] = a[r];
-            sb[threadIdx.x + 64 * r] = b[r];
-        }
-    }
+    stage_aes_tables64(te0, sb, te0g, sbg);
     lds_barrier();
     const KeyArg key = chunk.keys[blockIdx.x];
     KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(chunk.slots[blockIdx.x]);
@@ -382,22 +417,7 @@ __global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t
         }
     }
     lds_barrier();
-    // H^(2^k) = F_k(H): lane k applies its Frobenius table (F_0 is the identity)
-    const int k = threadIdx.x;
-    if (k < kPowLevels) {
-        const u32x4 H = u32x4{h_sh[0], h_sh[1], h_sh[2], h_sh[3]};
-        u32x4 r = H;
-        if (k > 0) {
-            const u32x4 *F = frob + (uint64_t)(k - 1) * 4096;
-            r = u32x4{0, 0, 0, 0};
-            for (int j = 0; j < 16; ++j)
-                r ^= F[j * 256 + byte_of(H, j)];
-        }
-        hd->hpow[k][0] = r.x;
-        hd->hpow[k][1] = r.y;
-        hd->hpow[k][2] = r.z;
-        hd->hpow[k][3] = r.w;
-    }
+    write_hpow(hd, h_sh, frob);
 }
 
 // Fixed-multiplier tables.  Block b < kTab4Levels builds the nibble-position
@@ -987,6 +1007,34 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         partials[d.tile_base + t] = a;
 }
 
+// T-tables into LDS: dword 16384 + 64*e + 16*t + c holds rotl(TE0[e], 8t)
+// for copy c = 0..15; thread q of NT writes the 16 copies of entries
+// (e, t) = (q >> 2, q & 3), q + NT, ..., with all loads issued first.  The
+// caller adds the barrier.
+template <int NT>
+__device__ __forceinline__ void stage_ttables(u32x4 *lds_v, const uint32_t *__restrict__ te0g)
+{
+    constexpr int kPer = (1024 + NT - 1) / NT;
+    uint32_t v[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int q = (int)threadIdx.x + r * NT;
+        v[r] = q < 1024 ? rotl32(te0g[q >> 2], 8 * (q & 3)) : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const int q = (int)threadIdx.x + r * NT;
+        if (q >= 1024)
+            break;
+        u32x4 *dst = lds_v + 4096 + 4 * q;  // dword 16384 + 64*(q >> 2) + 16*(q & 3)
+        const u32x4 x = {v[r], v[r], v[r], v[r]};
+        dst[0] = x;
+        dst[1] = x;
+        dst[2] = x;
+        dst[3] = x;
+    }
+}
+
 // Kernel variants (each a kernel of its own, so that the extra work of one
 // leaves the register allocation of the others alone): GCM; counter mode
 // only; GCM with the GHASH-only pass over whole AAD rows, for single messages
@@ -1011,29 +1059,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
     if (GH && blockIdx.x == 0 && threadIdx.x == 0)
         counters[0] = 0;  // reject count for this launch (read by the zero-fill)
 
-    {
-        // T-tables: dword 16384 + 64*e + 16*t + c holds rotl(TE0[e], 8t); work
-        // item (e, t) writes the 16 copies of one entry, all loads issued first
-        constexpr int kPer = (1024 + WAVES * 64 - 1) / (WAVES * 64);
-        uint32_t v[kPer];
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int q = (int)threadIdx.x + r * WAVES * 64;
-            v[r] = q < 1024 ? rotl32(te0g[q >> 2], 8 * (q & 3)) : 0u;
-        }
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const int q = (int)threadIdx.x + r * WAVES * 64;
-            if (q >= 1024)
-                break;
-            u32x4 *dst = lds_v + 4096 + 4 * q;  // dword 16384 + 64*(q >> 2) + 16*(q & 3)
-            const u32x4 x = {v[r], v[r], v[r], v[r]};
-            dst[0] = x;
-            dst[1] = x;
-            dst[2] = x;
-            dst[3] = x;
-        }
-    }
+    stage_ttables<WAVES * 64>(lds_v, te0g);
     // with GHASH, the table staging of the first work item below starts and
     // ends with a barrier, which also publishes the T-tables
     if (!GH)
@@ -1271,6 +1297,328 @@ __global__ __launch_bounds__(256) void k_gcm_zerofill(const MsgDesc *__restrict_
     }
 }
 
+// ---------------------------------------------------------------- AES-GCM-SIV (RFC 8452)
+//
+// POLYVAL through GHASH: with BR the reversal of a block's 16 bytes,
+// POLYVAL(H, X_1..X_s) = BR(GHASH_H'(BR(X_1), ..., BR(X_s))) where H' is
+// BR(H) times x in GHASH's field (RFC 8452 appendix A).  A per-message slot
+// holds the derived encryption key's round keys and H' with every GHASH table
+// of an ordinary key slot, so the tiles, the lane fix-ups and the combine
+// tree run unchanged on byte-reversed blocks.  The counter block is the tag
+// with the top bit of byte 15 set; its bytes 0..3 (memory-order dword 0) are
+// a little-endian 32-bit counter, so dword 0 is the column that varies, where
+// GCM's counter varies column 3.
+
+struct SivArg {
+    uint32_t nonce[3];
+    uint32_t pad;
+};
+
+__device__ __forceinline__ u32x4 rev_block(u32x4 x) { return u32x4{bswap32(x.w), bswap32(x.z), bswap32(x.y), bswap32(x.x)}; }
+
+// One wave: the message keys from the key-generating key in slot `kgk`
+// (first halves of AES_KGK(LE32(i) || nonce): i = 0, 1 the authentication
+// key, i = 2, 3 (and 4, 5 for a 256-bit key) the encryption key), expanded
+// into slot `out` with H' and its powers H'^(2^k).  With `tag_in` (decrypt)
+// the counter block is also formed from the received tag at `ctr_out`.
+__global__ __launch_bounds__(64) void k_siv_derive(uint64_t kgk, SivArg na, uint64_t out, const uint8_t *tag_in,
+                                                   u32x4 *ctr_out, const uint32_t *te0g, const uint32_t *sbg,
+                                                   const u32x4 *__restrict__ frob)
+{
+    __shared__ uint32_t te0[256], sb[256];
+    __shared__ uint32_t h_sh[4];
+    stage_aes_tables64(te0, sb, te0g, sbg);
+    lds_barrier();
+    KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(out);
+    if (threadIdx.x == 0) {
+        const KeySlotHdr *kh = reinterpret_cast<const KeySlotHdr *>(kgk);
+        const bool k128 = kh->nr == 10;
+        uint32_t rkw[4 * (kMaxNr + 1)];
+        for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
+            rkw[i] = kh->rk[i];
+        uint32_t half[12];
+        for (int i = 0; i < 6; ++i) {
+            const uint32_t in[4] = {(uint32_t)i, na.nonce[0], na.nonce[1], na.nonce[2]};
+            uint32_t o[4];
+            if (k128)
+                aes_block<10>(rkw, te0, sb, in, o);
+            else
+                aes_block<14>(rkw, te0, sb, in, o);
+            half[2 * i] = o[0];
+            half[2 * i + 1] = o[1];
+        }
+        uint32_t w[4 * (kMaxNr + 1)];
+        if (k128)
+            expand_key<4>(half + 4, hd, sb, w);
+        else
+            expand_key<8>(half + 4, hd, sb, w);
+        const uint32_t br[4] = {bswap32(half[3]), bswap32(half[2]), bswap32(half[1]), bswap32(half[0])};
+        const u32x4 hp = poly_to_mem(poly_mul_xi(mem_to_poly(br), 1));
+        const uint32_t hw[4] = {hp.x, hp.y, hp.z, hp.w};
+        for (int i = 0; i < 4; ++i) {
+            hd->h[i] = hw[i];
+            h_sh[i] = hw[i];
+        }
+        if (tag_in) {
+            uint32_t c[4] = {0, 0, 0, 0};
+            for (int k = 0; k < 16; ++k)
+                c[k >> 2] |= (uint32_t)tag_in[k] << (8 * (k & 3));
+            *ctr_out = u32x4{c[0], c[1], c[2], c[3] | 0x80000000u};
+        }
+    }
+    lds_barrier();
+    write_hpow(hd, h_sh, frob);
+}
+
+// One wave: S = BR(*g) is the POLYVAL value; S ^= nonce in bytes 0..11, top
+// bit of byte 15 cleared; tag = AES(S) under the slot's encryption key.
+// Encrypt (tag_out): write the tag and the counter block.  Decrypt: compare
+// all 16 bytes with tag_in without early exit, write the accept flag and the
+// reject count the zero-fill reads.
+__global__ __launch_bounds__(64) void k_siv_tag(uint64_t slot, const u32x4 *g, SivArg na, uint8_t *tag_out,
+                                                u32x4 *ctr_out, const uint8_t *tag_in, int32_t *ok,
+                                                uint32_t *counters, const uint32_t *te0g, const uint32_t *sbg)
+{
+    __shared__ uint32_t te0[256], sb[256];
+    stage_aes_tables64(te0, sb, te0g, sbg);
+    lds_barrier();
+    if (threadIdx.x != 0)
+        return;
+    const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
+    uint32_t rkw[4 * (kMaxNr + 1)];
+    for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
+        rkw[i] = hd->rk[i];
+    const u32x4 sv = rev_block(*g);
+    const uint32_t in[4] = {sv.x ^ na.nonce[0], sv.y ^ na.nonce[1], sv.z ^ na.nonce[2], sv.w & 0x7fffffffu};
+    uint32_t t[4];
+    if (hd->nr == 10)
+        aes_block<10>(rkw, te0, sb, in, t);
+    else
+        aes_block<14>(rkw, te0, sb, in, t);
+    if (tag_out) {
+        for (int k = 0; k < 16; ++k)
+            tag_out[k] = (uint8_t)(t[k >> 2] >> (8 * (k & 3)));
+        *ctr_out = u32x4{t[0], t[1], t[2], t[3] | 0x80000000u};
+        return;
+    }
+    uint32_t diff = 0;
+    for (int k = 0; k < 16; ++k)
+        diff |= ((t[k >> 2] >> (8 * (k & 3))) & 0xffu) ^ tag_in[k];
+    const int32_t accept = diff == 0 ? 1 : 0;
+    *ok = accept;
+    counters[0] = accept ? 0u : 1u;
+    counters[1] = 0u;
+}
+
+struct SivCtx {
+    uint32_t u0, u1, u2, u3;  // round-1 columns without the counter dword's bytes (unrotated, uniform)
+    uint32_t rk0;             // round key 0, column 0
+};
+
+// Keystream block for LE counter value `ctr` in dword 0: round 1 needs the
+// four lookups of the counter dword's bytes only.
+template <int NR>
+__device__ __forceinline__ u32x4 aes_siv_ctr(uint32_t ctr, const SivCtx &c, const CONST_AS uint32_t *rk,
+                                             const uint8_t *lds, const LaneK &lk)
+{
+    const uint32_t w0 = rotr_by(ctr ^ c.rk0, lk.rot);
+    const uint32_t s0 = rotr_by(c.u0, lk.rot) ^ LK(0, w0);
+    const uint32_t s1 = rotr_by(c.u1, lk.rot) ^ LK(3, w0);
+    const uint32_t s2 = rotr_by(c.u2, lk.rot) ^ LK(2, w0);
+    const uint32_t s3 = rotr_by(c.u3, lk.rot) ^ LK(1, w0);
+    return aes_rounds<2, NR>(s0, s1, s2, s3, rk, lds, lk);
+}
+
+// Counter-mode caching through round 2, as for GCM: with counter bytes 1..3
+// fixed, round 1 leaves columns 1..3 fixed and column 0 depends on the low
+// counter byte only, so round 2 takes one lookup per column.
+__device__ __forceinline__ Ctr2 siv_round2(uint32_t hi, const SivCtx &c, const CONST_AS uint32_t *rk,
+                                           const CONST_AS uint32_t *te)
+{
+    const uint32_t v = (hi << 8) ^ c.rk0;  // counter bytes 1..3 with the key (byte 0 unused)
+    const uint32_t u1 = c.u1 ^ te_s(te, 3, B3(v));
+    const uint32_t u2 = c.u2 ^ te_s(te, 2, B2(v));
+    const uint32_t u3 = c.u3 ^ te_s(te, 1, B1(v));
+    Ctr2 q;
+    q.v0 = te_s(te, 1, B1(u1)) ^ te_s(te, 2, B2(u2)) ^ te_s(te, 3, B3(u3)) ^ rk[8];
+    q.v1 = te_s(te, 0, B0(u1)) ^ te_s(te, 1, B1(u2)) ^ te_s(te, 2, B2(u3)) ^ rk[9];
+    q.v2 = te_s(te, 0, B0(u2)) ^ te_s(te, 1, B1(u3)) ^ te_s(te, 3, B3(u1)) ^ rk[10];
+    q.v3 = te_s(te, 0, B0(u3)) ^ te_s(te, 2, B2(u1)) ^ te_s(te, 3, B3(u2)) ^ rk[11];
+    return q;
+}
+
+template <int NR>
+__device__ __forceinline__ u32x4 aes_siv_ctr2(uint32_t ctr, const Ctr2 &q, const SivCtx &c,
+                                              const CONST_AS uint32_t *rk, const uint8_t *lds, const LaneK &lk)
+{
+    const uint32_t w0 = rotr_by(ctr ^ c.rk0, lk.rot);       // byte 0: low counter byte ^ key
+    const uint32_t x0 = rotr_by(c.u0, lk.rot) ^ LK(0, w0);  // round-1 column 0
+    const uint32_t s0 = rotr_by(q.v0, lk.rot) ^ LK(0, x0);
+    const uint32_t s1 = rotr_by(q.v1, lk.rot) ^ LK(3, x0);
+    const uint32_t s2 = rotr_by(q.v2, lk.rot) ^ LK(2, x0);
+    const uint32_t s3 = rotr_by(q.v3, lk.rot) ^ LK(1, x0);
+    return aes_rounds<3, NR>(s0, s1, s2, s3, rk, lds, lk);
+}
+
+// The three tile passes: the POLYVAL of AAD and plaintext (encrypt, first
+// pass), counter mode alone (encrypt, second pass, once the tag is known),
+// and counter mode fused with the POLYVAL of its output (decrypt-verify).
+constexpr int kSivHash = 0, kSivCtr = 1, kSivDec = 2;
+
+// Wave tile t of one message, laid out as in wave_tile: rows of 64 blocks,
+// lane l on block 64r + l, per-lane Horner with H'^64 over byte-reversed
+// blocks, fix-up by H'^(63 - l), XOR across the wave.  The GHASH sequence is
+// AAD blocks, data blocks and the length block LE64(8|A|) || LE64(8|P|),
+// each zero-padded and reversed.
+template <int NR, int PASS>
+__device__ void wave_tile_siv(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
+                              const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
+{
+    constexpr bool GH = PASS != kSivCtr, AES = PASS != kSivHash;
+    const int lane = threadIdx.x & 63;
+    const CONST_AS uint32_t *te = cptr<uint32_t>(te0g);
+    const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
+    const CONST_AS uint32_t *rk = rk_base;
+    SivCtx c = {0, 0, 0, 0, 0};
+    uint32_t c0 = 0;
+    if (AES) {
+        const CONST_AS uint32_t *cw = cptr<uint32_t>(reinterpret_cast<const void *>(d.j0));
+        c0 = cw[0];
+        const uint32_t s1 = cw[1] ^ rk[1], s2 = cw[2] ^ rk[2], s3 = cw[3] ^ rk[3];
+        c.u0 = uniform(te_u(lds, 1, B1(s1)) ^ te_u(lds, 2, B2(s2)) ^ te_u(lds, 3, B3(s3)) ^ rk[4]);
+        c.u1 = uniform(te_u(lds, 0, B0(s1)) ^ te_u(lds, 1, B1(s2)) ^ te_u(lds, 2, B2(s3)) ^ rk[5]);
+        c.u2 = uniform(te_u(lds, 0, B0(s2)) ^ te_u(lds, 1, B1(s3)) ^ te_u(lds, 3, B3(s1)) ^ rk[6]);
+        c.u3 = uniform(te_u(lds, 0, B0(s3)) ^ te_u(lds, 2, B2(s1)) ^ te_u(lds, 3, B3(s2)) ^ rk[7]);
+        c.rk0 = rk[0];
+    }
+
+    const uint64_t B = 1ull << d.log2B;
+    const uint32_t R = (uint32_t)(B >> 6);
+    const int64_t vbase = (int64_t)(t * B) - (int64_t)d.z;  // sequence index of lane 0, row 0
+    const uint32_t r0 = vbase < 0 ? (uint32_t)((uint64_t)(-vbase) >> 6) : 0u;
+    const int64_t na = (int64_t)d.na;
+    const int64_t nfull = (int64_t)(d.len >> 4);
+    const int64_t ndat = (int64_t)d.n;
+    const uint8_t *__restrict__ in = reinterpret_cast<const uint8_t *>(d.in);
+    uint8_t *__restrict__ out = reinterpret_cast<uint8_t *>(d.out);
+    const GLOBAL_AS u32x4 *in_g = gptr<const u32x4>(d.in);
+    GLOBAL_AS u32x4 *out_g = gptr<u32x4>(d.out);
+
+    u32x4 a = {0, 0, 0, 0};
+    auto boundary_row = [&](int64_t v0) {
+        const int64_t v = v0 + lane;
+        const uint64_t j = (uint64_t)(v - na);
+        u32x4 ks = {0, 0, 0, 0};
+        if (AES)
+            ks = aes_siv_ctr<NR>((uint32_t)j + c0, c, rk, lds, lk);
+        u32x4 X = {0, 0, 0, 0};
+        if (GH && v >= 0 && v < na) {
+            X = load_block_partial(reinterpret_cast<const uint8_t *>(d.aad), (uint64_t)v, d.aad_len);
+        } else if (v >= na && v < na + ndat) {
+            const u32x4 x = load_block_partial(in, j, d.len);
+            if (AES) {
+                const u32x4 o = x ^ ks;
+                store_block_partial(out, j, d.len, o);
+                X = mask_block(o, j, d.len);
+            } else {
+                X = x;
+            }
+        } else if (GH && v == na + ndat) {
+            const uint64_t abits = d.aad_len * 8, pbits = d.len * 8;
+            X = u32x4{(uint32_t)abits, (uint32_t)(abits >> 32), (uint32_t)pbits, (uint32_t)(pbits >> 32)};
+        }
+        if (GH)
+            a = ghash_mul8(a, rev_block(X), lds, gk);
+    };
+
+    uint32_t hc = 0xffffffffu;
+    Ctr2 cur = {0, 0, 0, 0};
+    for (uint32_t r = r0; r < R; ++r) {
+        rk = rk_base;
+        asm volatile("" : "+s"(rk));
+        const int64_t v0 = vbase + 64 * (int64_t)r;
+        if (v0 >= na && v0 + 64 <= na + nfull) {
+            const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
+            const u32x4 x = in_g[j];
+            if (AES) {
+                const uint32_t base = (uint32_t)(v0 - na) + c0;
+                const uint32_t h = base >> 8;
+                if (h != hc) {
+                    cur = siv_round2(h, c, rk, te);
+                    hc = h;
+                }
+                Ctr2 q = cur;
+                if ((base & 255u) > 192u) {
+                    const uint32_t h1 = (h + 1u) & 0xffffffu;
+                    const Ctr2 nxt = siv_round2(h1, c, rk, te);
+                    const bool up = (base & 255u) + (uint32_t)lane > 255u;
+                    q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
+                    cur = nxt;
+                    hc = h1;
+                }
+                const u32x4 o = x ^ aes_siv_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
+                __builtin_nontemporal_store(o, out_g + j);
+                if (GH)
+                    a = ghash_mul8(a, rev_block(o), lds, gk);
+            } else {
+                a = ghash_mul8(a, rev_block(x), lds, gk);
+            }
+        } else {
+            boundary_row(v0);
+        }
+    }
+    if (!GH)
+        return;
+    a = gf_mul_comb(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLanePowOff)[63 - lane]);
+    a = wave_xor_reduce(a);
+    if (lane == 0)
+        partials[d.tile_base + t] = a;
+}
+
+// One message, tiles [d.tile_lo, d.tile_hi): workgroup item it covers WAVES
+// consecutive tiles.  LDS as in k_gcm_tiles (GHASH table of the message slot,
+// T-tables), each staged only by the passes that read it.
+template <int WAVES, int PASS>
+__global__ __launch_bounds__(WAVES * 64) void k_siv_tiles(MsgDesc d, uint32_t n_items,
+                                                          const uint32_t *__restrict__ te0g,
+                                                          u32x4 *__restrict__ partials)
+{
+    constexpr bool GH = PASS != kSivCtr, AES = PASS != kSivHash;
+    __shared__ u32x4 lds_v[8192];
+    const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
+    if (AES)
+        stage_ttables<WAVES * 64>(lds_v, te0g);
+    if (GH) {
+        const GLOBAL_AS u32x4 *src = gptr<const u32x4>(d.slot + kSlotTab8Off);
+        constexpr int kPer = (4096 + WAVES * 64 - 1) / (WAVES * 64);
+        u32x4 st[kPer];
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint32_t q = threadIdx.x + r * WAVES * 64;
+            st[r] = q < 4096u ? src[q] : u32x4{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+            const uint32_t q = threadIdx.x + r * WAVES * 64;
+            if (q < 4096u)
+                lds_v[q] = st[r];
+        }
+    }
+    lds_barrier();
+    const LaneK lk = lane_constants(threadIdx.x & 63);
+    const GhK gk = gh_constants(threadIdx.x & 63);
+    const uint32_t wave = uniform(threadIdx.x >> 6);
+    for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
+        const uint64_t t = d.tile_lo + (uint64_t)it * WAVES + wave;
+        if (t < d.tile_hi) {
+            if (d.nr == 10)
+                wave_tile_siv<10, PASS>(d, t, lds, lk, gk, te0g, partials);
+            else
+                wave_tile_siv<14, PASS>(d, t, lds, lk, gk, te0g, partials);
+        }
+    }
+}
+
 // ---------------------------------------------------------------- host-side launchers
 
 hipError_t launch_init_tables(uint32_t *te0, uint32_t *sbox, void *frob, hipStream_t s)
@@ -1402,6 +1750,68 @@ hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const ui
     else
         hipLaunchKernelGGL(k_gcm_zerofill<false>, dim3(grid), dim3(256), 0, s, nullptr, *single, counters);
     return hipGetLastError();
+}
+
+hipError_t launch_siv_derive(uint64_t kgk_slot, const uint8_t nonce[12], uint64_t out_slot, const uint8_t *tag_in,
+                             void *ctr_out, const uint32_t *te0, const uint32_t *sbox, const void *frob, hipStream_t s)
+{
+    SivArg a{};
+    for (int i = 0; i < 3; ++i)
+        a.nonce[i] = (uint32_t)nonce[4 * i] | ((uint32_t)nonce[4 * i + 1] << 8) | ((uint32_t)nonce[4 * i + 2] << 16) |
+                     ((uint32_t)nonce[4 * i + 3] << 24);
+    hipLaunchKernelGGL(k_siv_derive, dim3(1), dim3(64), 0, s, kgk_slot, a, out_slot, tag_in,
+                       reinterpret_cast<u32x4 *>(ctr_out), te0, sbox, reinterpret_cast<const u32x4 *>(frob));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    SlotChunk sc{};
+    sc.slots[0] = out_slot;
+    hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLanePows, 1), dim3(256), 0, s, sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_siv_tag(uint64_t slot, const void *g, const uint8_t nonce[12], uint8_t *tag_out, void *ctr_out,
+                          const uint8_t *tag_in, int32_t *ok, uint32_t *counters, const uint32_t *te0,
+                          const uint32_t *sbox, hipStream_t s)
+{
+    SivArg a{};
+    for (int i = 0; i < 3; ++i)
+        a.nonce[i] = (uint32_t)nonce[4 * i] | ((uint32_t)nonce[4 * i + 1] << 8) | ((uint32_t)nonce[4 * i + 2] << 16) |
+                     ((uint32_t)nonce[4 * i + 3] << 24);
+    hipLaunchKernelGGL(k_siv_tag, dim3(1), dim3(64), 0, s, slot, reinterpret_cast<const u32x4 *>(g), a, tag_out,
+                       reinterpret_cast<u32x4 *>(ctr_out), tag_in, ok, counters, te0, sbox);
+    return hipGetLastError();
+}
+
+template <int WAVES>
+static hipError_t launch_siv_tiles_w(int pass, const MsgDesc &d, uint32_t n_items, const uint32_t *te0, u32x4 *p,
+                                     uint32_t grid, hipStream_t s)
+{
+    if (pass == kSivHash)
+        hipLaunchKernelGGL((k_siv_tiles<WAVES, kSivHash>), dim3(grid), dim3(WAVES * 64), 0, s, d, n_items, te0, p);
+    else if (pass == kSivCtr)
+        hipLaunchKernelGGL((k_siv_tiles<WAVES, kSivCtr>), dim3(grid), dim3(WAVES * 64), 0, s, d, n_items, te0, p);
+    else
+        hipLaunchKernelGGL((k_siv_tiles<WAVES, kSivDec>), dim3(grid), dim3(WAVES * 64), 0, s, d, n_items, te0, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_siv_tiles(int waves, int pass, const MsgDesc &d, uint32_t n_items, const uint32_t *te0,
+                            void *partials, uint32_t grid, hipStream_t s)
+{
+    u32x4 *p = reinterpret_cast<u32x4 *>(partials);
+    if (pass < kSivHash || pass > kSivDec)
+        return hipErrorInvalidValue;
+    switch (waves) {
+    case 8:
+        return launch_siv_tiles_w<8>(pass, d, n_items, te0, p, grid, s);
+    case 12:
+        return launch_siv_tiles_w<12>(pass, d, n_items, te0, p, grid, s);
+    case 16:
+        return launch_siv_tiles_w<16>(pass, d, n_items, te0, p, grid, s);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace gcm

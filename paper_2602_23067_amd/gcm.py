@@ -160,6 +160,10 @@ def load() -> ctypes.CDLL:
         "gcm_stream_final": ([vp, vp, vp, vp], ctypes.c_int),
         "gcm_stream_destroy": ([vp], ctypes.c_int),
         "gcm_decrypt_verify_ex": ([vp, vp, sz, vp, sz, vp, u64, vp, u64, vp, sz, vp, i32p, vp], ctypes.c_int),
+        "gcm_siv_workspace_size": ([vp, u64, u64], u64),
+        "gcm_siv_encrypt_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, u64, vp], ctypes.c_int),
+        "gcm_siv_decrypt_verify_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, vp, u64, vp],
+                                         ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -406,6 +410,37 @@ class Context:
                                                0 if aad is None else aad.numel(), _dev(ct), ct.numel(),
                                                _dev(tag_d), _dev(pt), accept_d.data_ptr(), _dev(workspace),
                                                workspace.numel(), _stream(stream)))
+
+    # -------------------------------------------------------- AES-GCM-SIV (RFC 8452)
+    def siv_workspace_size(self, length: int, aad_len: int) -> int:
+        return int(load().gcm_siv_workspace_size(self._h, length, aad_len))
+
+    def _siv_ws(self, length: int, aad_len: int, workspace):
+        if workspace is not None:
+            return workspace
+        import torch
+        n = self.siv_workspace_size(length, aad_len)
+        return torch.empty(n, dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def siv_encrypt_async(self, slot: int, nonce: bytes, aad, pt, ct, tag_d, workspace=None, stream=None):
+        """Enqueue GCM-SIV encryption of device tensors; returns the workspace
+        used (keep it alive until the stream has passed the call)."""
+        n = 0 if pt is None else pt.numel()
+        na = 0 if aad is None else aad.numel()
+        ws = self._siv_ws(n, na, workspace)
+        _check(load().gcm_siv_encrypt_async(self._h, slot, _host(nonce), len(nonce), _dev(aad), na, _dev(pt), n,
+                                            _dev(ct), _dev(tag_d), _dev(ws), ws.numel(), _stream(stream)))
+        return ws
+
+    def siv_decrypt_verify_async(self, slot: int, nonce: bytes, aad, ct, tag_d, pt, accept_d, workspace=None,
+                                 stream=None):
+        n = 0 if ct is None else ct.numel()
+        na = 0 if aad is None else aad.numel()
+        ws = self._siv_ws(n, na, workspace)
+        _check(load().gcm_siv_decrypt_verify_async(self._h, slot, _host(nonce), len(nonce), _dev(aad), na,
+                                                   _dev(ct), n, _dev(tag_d), _dev(pt), accept_d.data_ptr(),
+                                                   _dev(ws), ws.numel(), _stream(stream)))
+        return ws
 
     # -------------------------------------------------------- measurement
     def profile_enable(self, on: bool = True) -> None:

@@ -27,7 +27,8 @@ def test_header_declares_the_boundary():
                  "gcm_ctr_xcrypt", "gcm_ctr_async", "gcm_gmac", "gcm_encrypt_host", "gcm_decrypt_verify_host",
                  "gcm_set_pipeline", "gcm_encrypt_ex", "gcm_decrypt_verify_ex",
                  "gcm_stream_begin", "gcm_stream_update", "gcm_stream_final", "gcm_stream_destroy",
-                 "gcm_fits_encrypt", "gcm_fits_decrypt", "gcm_fits_free", "gcm_fits_nonce"):
+                 "gcm_fits_encrypt", "gcm_fits_decrypt", "gcm_fits_free", "gcm_fits_nonce",
+                 "gcm_siv_workspace_size", "gcm_siv_encrypt_async", "gcm_siv_decrypt_verify_async"):
         assert need in names
 
 
