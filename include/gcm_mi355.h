@@ -37,7 +37,9 @@
  *    GCM_E_ALIAS.
  *  - The caller owns every buffer.  The context owns its key table and its
  *    internal scratch.  No call keeps a caller pointer after it returns.
- *  - No C++ exception crosses this interface.
+ *  - No C++ exception crosses this interface: a failed host allocation inside
+ *    the runtime returns GCM_E_NOMEM, any other host runtime failure
+ *    GCM_E_INTERNAL, with the message in gcm_last_error().
  */
 #ifndef GCM_MI355_H
 #define GCM_MI355_H
@@ -59,6 +61,7 @@ extern "C" {
 #define GCM_E_BUSY (-7)    /* no free key slot / serving queue full */
 #define GCM_E_ALIAS (-8)   /* in and out overlap without being equal */
 #define GCM_E_SLOT (-9)    /* key slot index not registered */
+#define GCM_E_INTERNAL (-10) /* a host runtime failure other than memory (e.g. a thread that cannot start) */
 
 typedef struct gcm_ctx gcm_ctx;
 

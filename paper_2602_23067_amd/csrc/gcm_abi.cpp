@@ -7,8 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <list>
 #include <mutex>
+#include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -20,16 +22,15 @@ using namespace gcm;
 
 // ---------------------------------------------------------------- errors
 
-static thread_local std::string g_last_error;
+// a fixed buffer: recording an error never allocates (and so never throws)
+static thread_local char g_last_error[512];
 
 int gcm::fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
     va_end(ap);
-    g_last_error = buf;
     return code;
 }
 
@@ -38,7 +39,20 @@ int gcm::fail_hip(hipError_t e, const char *what)
     return fail(GCM_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-extern "C" const char *gcm_last_error(void) { return g_last_error.c_str(); }
+int gcm::abi_exception() noexcept
+{
+    try {
+        throw;
+    } catch (const std::bad_alloc &) {
+        return fail(GCM_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(GCM_E_INTERNAL, "host runtime failure: %s", e.what());
+    } catch (...) {
+        return fail(GCM_E_INTERNAL, "host runtime failure");
+    }
+}
+
+extern "C" const char *gcm_last_error(void) { return g_last_error; }
 
 // placeholder IV for fill_desc when set_iv fills the descriptor's IV afterwards
 static const uint8_t kZeroIv[12] = {0};
@@ -69,103 +83,109 @@ void gcm::ctx_free(gcm_ctx *ctx, void *p, uint64_t bytes)
 
 extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_bytes, uint32_t key_slots)
 {
-    if (!out)
-        return fail(GCM_E_ARG, "gcm_ctx_create: out is NULL");
-    *out = nullptr;
-    if (key_slots == 0 || key_slots > (1u << 20))
-        return fail(GCM_E_ARG, "gcm_ctx_create: key_slots must be in 1..2^20");
-    int ndev = 0;
-    hipError_t e = hipGetDeviceCount(&ndev);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipGetDeviceCount");
-    if (device < 0 || device >= ndev)
-        return fail(GCM_E_ARG, "gcm_ctx_create: device %d out of range (%d devices)", device, ndev);
-    e = hipSetDevice(device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-
-    gcm_ctx *ctx = new (std::nothrow) gcm_ctx();
-    if (!ctx)
-        return fail(GCM_E_NOMEM, "gcm_ctx_create: host allocation failed");
-    ctx->device = device;
-    ctx->budget = hbm_budget_bytes;
-    ctx->n_slots = key_slots;
-    int cus = 0;
-    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
-    ctx->cu_count = cus > 0 ? cus : 1;
-
-    int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), 2 * 256 * sizeof(uint32_t));
-    if (rc == GCM_OK)
-        rc = ctx_alloc(ctx, &ctx->d_frob, frob_table_bytes());
-    if (rc == GCM_OK)
-        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_slots), kSlotBytes * key_slots);
-    if (rc == GCM_OK)
-        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_io), 256);
-    if (rc == GCM_OK) {
-        e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_io), 256, hipHostMallocDefault);
+    GCM_ABI_TRY
+        if (!out)
+            return fail(GCM_E_ARG, "gcm_ctx_create: out is NULL");
+        *out = nullptr;
+        if (key_slots == 0 || key_slots > (1u << 20))
+            return fail(GCM_E_ARG, "gcm_ctx_create: key_slots must be in 1..2^20");
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
         if (e != hipSuccess)
-            rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
-    }
-    if (rc == GCM_OK) {
-        e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, ctx->d_frob, nullptr);
-        if (e == hipSuccess)
-            e = hipDeviceSynchronize();
+            return fail_hip(e, "hipGetDeviceCount");
+        if (device < 0 || device >= ndev)
+            return fail(GCM_E_ARG, "gcm_ctx_create: device %d out of range (%d devices)", device, ndev);
+        e = hipSetDevice(device);
         if (e != hipSuccess)
-            rc = fail_hip(e, "AES table initialisation");
-    }
-    if (rc != GCM_OK) {
-        gcm_ctx_destroy(ctx);
-        return rc;
-    }
-    ctx->slot_used.assign(key_slots, 0);
-    ctx->slot_nr.assign(key_slots, 0);
-    ctx->cache_cap = std::max<uint32_t>(1, std::min<uint32_t>(16, key_slots / 2 ? key_slots / 2 : 1));
-    *out = ctx;
-    return GCM_OK;
+            return fail_hip(e, "hipSetDevice");
+
+        gcm_ctx *ctx = new (std::nothrow) gcm_ctx();
+        if (!ctx)
+            return fail(GCM_E_NOMEM, "gcm_ctx_create: host allocation failed");
+        ctx->device = device;
+        ctx->budget = hbm_budget_bytes;
+        ctx->n_slots = key_slots;
+        int cus = 0;
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+        ctx->cu_count = cus > 0 ? cus : 1;
+
+        int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), 2 * 256 * sizeof(uint32_t));
+        if (rc == GCM_OK)
+            rc = ctx_alloc(ctx, &ctx->d_frob, frob_table_bytes());
+        if (rc == GCM_OK)
+            rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_slots), kSlotBytes * key_slots);
+        if (rc == GCM_OK)
+            rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_io), 256);
+        if (rc == GCM_OK) {
+            e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_io), 256, hipHostMallocDefault);
+            if (e != hipSuccess)
+                rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        }
+        if (rc == GCM_OK) {
+            e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, ctx->d_frob, nullptr);
+            if (e == hipSuccess)
+                e = hipDeviceSynchronize();
+            if (e != hipSuccess)
+                rc = fail_hip(e, "AES table initialisation");
+        }
+        if (rc != GCM_OK) {
+            gcm_ctx_destroy(ctx);
+            return rc;
+        }
+        ctx->slot_used.assign(key_slots, 0);
+        ctx->slot_nr.assign(key_slots, 0);
+        ctx->cache_cap = std::max<uint32_t>(1, std::min<uint32_t>(16, key_slots / 2 ? key_slots / 2 : 1));
+        *out = ctx;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "gcm_ctx_destroy: NULL context");
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    ctx_free(ctx, ctx->d_tables, 2 * 256 * sizeof(uint32_t));
-    ctx_free(ctx, ctx->d_frob, frob_table_bytes());
-    ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
-    ctx_free(ctx, ctx->d_io, 256);
-    ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
-    pipeline_release(ctx);
-    for (auto &pr : ctx->prof_pending) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    for (auto &pr : ctx->prof_free) {
-        (void)hipEventDestroy(pr.first);
-        (void)hipEventDestroy(pr.second);
-    }
-    if (ctx->h_io)
-        (void)hipHostFree(ctx->h_io);
-    delete ctx;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_ctx_destroy: NULL context");
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        ctx_free(ctx, ctx->d_tables, 2 * 256 * sizeof(uint32_t));
+        ctx_free(ctx, ctx->d_frob, frob_table_bytes());
+        ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
+        ctx_free(ctx, ctx->d_io, 256);
+        ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+        pipeline_release(ctx);
+        for (auto &pr : ctx->prof_pending) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        for (auto &pr : ctx->prof_free) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+        if (ctx->h_io)
+            (void)hipHostFree(ctx->h_io);
+        delete ctx;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group,
                               uint32_t groups_per_cu)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "gcm_set_launch: NULL context");
-    if (log2_tile_blocks && (log2_tile_blocks < 6 || log2_tile_blocks > 20))
-        return fail(GCM_E_ARG, "gcm_set_launch: log2_tile_blocks must be 0 or 6..20");
-    if (waves_per_group && waves_per_group != 8 && waves_per_group != 12 && waves_per_group != 16)
-        return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 8, 12 or 16");
-    if (groups_per_cu > 64)
-        return fail(GCM_E_ARG, "gcm_set_launch: groups_per_cu must be <= 64");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->cfg_log2B = log2_tile_blocks;
-    ctx->cfg_waves = waves_per_group;
-    ctx->cfg_gpc = groups_per_cu;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_set_launch: NULL context");
+        if (log2_tile_blocks && (log2_tile_blocks < 6 || log2_tile_blocks > 20))
+            return fail(GCM_E_ARG, "gcm_set_launch: log2_tile_blocks must be 0 or 6..20");
+        if (waves_per_group && waves_per_group != 8 && waves_per_group != 12 && waves_per_group != 16)
+            return fail(GCM_E_ARG, "gcm_set_launch: waves_per_group must be 0, 8, 12 or 16");
+        if (groups_per_cu > 64)
+            return fail(GCM_E_ARG, "gcm_set_launch: groups_per_cu must be <= 64");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->cfg_log2B = log2_tile_blocks;
+        ctx->cfg_waves = waves_per_group;
+        ctx->cfg_gpc = groups_per_cu;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 // ---------------------------------------------------------------- keys
@@ -206,43 +226,49 @@ static bool valid_key_len(size_t n) { return n == 16 || n == 24 || n == 32; }
 
 extern "C" int gcm_key_register(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot_out, void *stream)
 {
-    if (!ctx || !key || !slot_out)
-        return fail(GCM_E_ARG, "gcm_key_register: NULL argument");
-    if (!valid_key_len(key_len))
-        return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
-    std::lock_guard<std::mutex> g(ctx->mu);
-    return register_key_locked(ctx, key, key_len, slot_out, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_TRY
+        if (!ctx || !key || !slot_out)
+            return fail(GCM_E_ARG, "gcm_key_register: NULL argument");
+        if (!valid_key_len(key_len))
+            return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        return register_key_locked(ctx, key, key_len, slot_out, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_key_register_many(gcm_ctx *ctx, const uint8_t *keys, const uint32_t *key_lens, uint32_t n,
                                      uint32_t *slots_out, void *stream)
 {
-    if (!ctx || (n && (!keys || !key_lens || !slots_out)))
-        return fail(GCM_E_ARG, "gcm_key_register_many: NULL argument");
-    std::vector<const uint8_t *> ptrs(n);
-    uint64_t off = 0;
-    for (uint32_t i = 0; i < n; ++i) {
-        if (!valid_key_len(key_lens[i]))
-            return fail(GCM_E_KEYLEN, "key %u: length %u is not 16, 24 or 32", i, key_lens[i]);
-        ptrs[i] = keys + off;
-        off += key_lens[i];
-    }
-    std::lock_guard<std::mutex> g(ctx->mu);
-    return register_keys_locked(ctx, ptrs.data(), key_lens, n, slots_out, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_TRY
+        if (!ctx || (n && (!keys || !key_lens || !slots_out)))
+            return fail(GCM_E_ARG, "gcm_key_register_many: NULL argument");
+        std::vector<const uint8_t *> ptrs(n);
+        uint64_t off = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            if (!valid_key_len(key_lens[i]))
+                return fail(GCM_E_KEYLEN, "key %u: length %u is not 16, 24 or 32", i, key_lens[i]);
+            ptrs[i] = keys + off;
+            off += key_lens[i];
+        }
+        std::lock_guard<std::mutex> g(ctx->mu);
+        return register_keys_locked(ctx, ptrs.data(), key_lens, n, slots_out, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_key_release(gcm_ctx *ctx, uint32_t slot)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "gcm_key_release: NULL context");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
-        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
-    for (auto &kv : ctx->cache)
-        if (kv.second == slot)
-            return fail(GCM_E_ARG, "key slot %u belongs to the one-shot key cache", slot);
-    ctx->slot_used[slot] = 0;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_key_release: NULL context");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+            return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+        for (auto &kv : ctx->cache)
+            if (kv.second == slot)
+                return fail(GCM_E_ARG, "key slot %u belongs to the one-shot key cache", slot);
+        ctx->slot_used[slot] = 0;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 // one-shot path: look the key up in the cache, expand it on a miss (LRU eviction
@@ -463,18 +489,20 @@ static uint32_t slot_nr(size_t key_len) { return (uint32_t)(key_len / 4 + 6); }
 
 extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len)
 {
-    if (!ctx)
-        return 0;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    uint32_t best = 64;
-    for (uint32_t nr : {10u, 12u, 14u}) {  // any key size the call may use
-        uint32_t log2B, waves, gpc;
-        message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
-        best = std::min(best, log2B);
-    }
-    const uint64_t T = (m + (1ull << best) - 1) >> best;
-    return workspace_bytes_for(T, 1);
+    GCM_ABI_TRY
+        if (!ctx)
+            return 0;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+        uint32_t best = 64;
+        for (uint32_t nr : {10u, 12u, 14u}) {  // any key size the call may use
+            uint32_t log2B, waves, gpc;
+            message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
+            best = std::min(best, log2B);
+        }
+        const uint64_t T = (m + (1ull << best) - 1) >> best;
+        return workspace_bytes_for(T, 1);
+    GCM_ABI_CATCH_VALUE(0)
 }
 
 int gcm::ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes)
@@ -534,8 +562,10 @@ extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv,
                                  uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d, uint8_t *tag_d,
                                  void *workspace_d, uint64_t workspace_bytes, void *stream)
 {
-    return async_common(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
-                        workspace_bytes, stream);
+    GCM_ABI_TRY
+        return async_common(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
+                            workspace_bytes, stream);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len,
@@ -543,8 +573,10 @@ extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8
                                         const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
                                         uint64_t workspace_bytes, void *stream)
 {
-    return async_common(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
-                        workspace_bytes, stream);
+    GCM_ABI_TRY
+        return async_common(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
+                            workspace_bytes, stream);
+    GCM_ABI_CATCH
 }
 
 // ---------------------------------------------------------------- one-shot entry points
@@ -618,8 +650,10 @@ extern "C" int gcm_encrypt_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, 
                               const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
                               uint8_t *tag_out, size_t tag_len, void *stream)
 {
-    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
-                   stream, tag_len);
+    GCM_ABI_TRY
+        return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
+                       stream, tag_len);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_decrypt_verify_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv,
@@ -627,23 +661,29 @@ extern "C" int gcm_decrypt_verify_ex(gcm_ctx *ctx, const uint8_t *key, size_t ke
                                      uint64_t len, const uint8_t *tag, size_t tag_len, uint8_t *pt_d, int *accept,
                                      void *stream)
 {
-    return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream,
-                   tag_len);
+    GCM_ABI_TRY
+        return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream,
+                       tag_len);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_encrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                            const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d,
                            uint8_t tag_out[16], void *stream)
 {
-    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
-                   stream);
+    GCM_ABI_TRY
+        return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, nullptr, tag_out, nullptr,
+                       stream);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                                   const uint8_t *aad_d, uint64_t aad_len, const uint8_t *ct_d, uint64_t len,
                                   const uint8_t tag[16], uint8_t *pt_d, int *accept, void *stream)
 {
-    return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream);
+    GCM_ABI_TRY
+        return oneshot(ctx, 1, key, key_len, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag, nullptr, accept, stream);
+    GCM_ABI_CATCH
 }
 
 // ---------------------------------------------------------------- counter mode only, GMAC
@@ -671,55 +711,61 @@ static int check_ctr_args(const void *iv, size_t iv_len, const uint8_t *in_d, ui
 extern "C" int gcm_ctr_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *in_d,
                              uint64_t len, uint8_t *out_d, void *stream)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "NULL argument");
-    int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
-    if (rc)
-        return rc;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
-        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-    return ctr_common(ctx, slot, ctx->slot_nr[slot], iv, in_d, len, out_d, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "NULL argument");
+        int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
+        if (rc)
+            return rc;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+            return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipSetDevice");
+        return ctr_common(ctx, slot, ctx->slot_nr[slot], iv, in_d, len, out_d, reinterpret_cast<hipStream_t>(stream));
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_ctr_xcrypt(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                               const uint8_t *in_d, uint64_t len, uint8_t *out_d, void *stream)
 {
-    if (!ctx || !key)
-        return fail(GCM_E_ARG, "NULL argument");
-    if (!valid_key_len(key_len))
-        return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
-    int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
-    if (rc)
-        return rc;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-    uint32_t slot;
-    rc = cached_slot_locked(ctx, key, key_len, &slot, s);
-    if (rc)
-        return rc;
-    rc = ctr_common(ctx, slot, slot_nr(key_len), iv, in_d, len, out_d, s);
-    if (rc)
-        return rc;
-    // like the other one-shot calls, return with the work done, so that the
-    // cached key slot may be reused by the next call on any stream
-    e = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipStreamSynchronize");
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx || !key)
+            return fail(GCM_E_ARG, "NULL argument");
+        if (!valid_key_len(key_len))
+            return fail(GCM_E_KEYLEN, "key length %zu is not 16, 24 or 32", key_len);
+        int rc = check_ctr_args(iv, iv_len, in_d, len, out_d);
+        if (rc)
+            return rc;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipSetDevice");
+        uint32_t slot;
+        rc = cached_slot_locked(ctx, key, key_len, &slot, s);
+        if (rc)
+            return rc;
+        rc = ctr_common(ctx, slot, slot_nr(key_len), iv, in_d, len, out_d, s);
+        if (rc)
+            return rc;
+        // like the other one-shot calls, return with the work done, so that the
+        // cached key slot may be reused by the next call on any stream
+        e = hipStreamSynchronize(s);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipStreamSynchronize");
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_gmac(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                         const uint8_t *aad_d, uint64_t aad_len, uint8_t tag_out[16], void *stream)
 {
-    return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, nullptr, 0, nullptr, nullptr, tag_out, nullptr,
-                   stream);
+    GCM_ABI_TRY
+        return oneshot(ctx, 0, key, key_len, iv, iv_len, aad_d, aad_len, nullptr, 0, nullptr, nullptr, tag_out, nullptr,
+                       stream);
+    GCM_ABI_CATCH
 }
 
 // ---------------------------------------------------------------- measurement
@@ -755,33 +801,37 @@ hipError_t gcm::prof_end(gcm_ctx *ctx, hipStream_t s)
 
 extern "C" int gcm_profile_enable(gcm_ctx *ctx, int enable)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "gcm_profile_enable: NULL context");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->prof = enable != 0;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_profile_enable: NULL context");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->prof = enable != 0;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_profile_read(gcm_ctx *ctx, uint64_t *launches, double *tile_ms_total)
 {
-    if (!ctx || !launches || !tile_ms_total)
-        return fail(GCM_E_ARG, "gcm_profile_read: NULL argument");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    double total = 0.0;
-    uint64_t n = 0;
-    for (auto &pr : ctx->prof_pending) {
-        hipError_t e = hipEventSynchronize(pr.second);
-        float ms = 0.f;
-        if (e == hipSuccess)
-            e = hipEventElapsedTime(&ms, pr.first, pr.second);
-        if (e != hipSuccess)
-            return fail_hip(e, "profile event");
-        total += ms;
-        ++n;
-        ctx->prof_free.push_back(pr);
-    }
-    ctx->prof_pending.clear();
-    *launches = n;
-    *tile_ms_total = total;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx || !launches || !tile_ms_total)
+            return fail(GCM_E_ARG, "gcm_profile_read: NULL argument");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        double total = 0.0;
+        uint64_t n = 0;
+        for (auto &pr : ctx->prof_pending) {
+            hipError_t e = hipEventSynchronize(pr.second);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, pr.first, pr.second);
+            if (e != hipSuccess)
+                return fail_hip(e, "profile event");
+            total += ms;
+            ++n;
+            ctx->prof_free.push_back(pr);
+        }
+        ctx->prof_pending.clear();
+        *launches = n;
+        *tile_ms_total = total;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }

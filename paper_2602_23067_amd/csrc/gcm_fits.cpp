@@ -351,186 +351,194 @@ int finish(gcm_fits_result *r, int rc)
 
 extern "C" int gcm_fits_nonce(uint8_t out[12])
 {
-    if (!out)
-        return fail(GCM_E_ARG, "NULL argument");
-    size_t got = 0;
-    while (got < 12) {
-        const ssize_t k = getrandom(out + got, 12 - got, 0);
-        if (k <= 0)
-            return fail(GCM_E_ARG, "getrandom failed");
-        got += (size_t)k;
-    }
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!out)
+            return fail(GCM_E_ARG, "NULL argument");
+        size_t got = 0;
+        while (got < 12) {
+            const ssize_t k = getrandom(out + got, 12 - got, 0);
+            if (k <= 0)
+                return fail(GCM_E_ARG, "getrandom failed");
+            got += (size_t)k;
+        }
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" void gcm_fits_free(gcm_fits_result *r)
 {
-    if (r && r->data) {
-        std::free(r->data);
-        r->data = nullptr;
-        r->size = 0;
-    }
+    GCM_ABI_TRY
+        if (r && r->data) {
+            std::free(r->data);
+            r->data = nullptr;
+            r->size = 0;
+        }
+    GCM_ABI_CATCH_VOID
 }
 
 extern "C" int gcm_fits_encrypt(gcm_ctx *ctx, const uint8_t *fits, uint64_t fits_len, const uint8_t *key_h,
                                 size_t key_h_len, const uint8_t *key_d, size_t key_d_len, const uint8_t nonce_h[12],
                                 const uint8_t nonce_d[12], gcm_fits_result *out)
 {
-    if (!out)
-        return fail(GCM_E_ARG, "NULL result");
-    std::memset(out, 0, sizeof *out);
-    if (!ctx || !fits || !key_h || !key_d || !nonce_h || !nonce_d)
-        return finish(out, fail(GCM_E_ARG, "NULL argument"));
-    Header h;
-    if (!read_header(fits, fits_len, 0, &h) || h.cards[0].compare(0, 9, "SIMPLE  =") != 0)
-        return finish(out, fail(GCM_E_ARG, "input is not a FITS file with a complete primary header"));
-    Structure s;
-    if (!get_int(h, "BITPIX", &s.bitpix) || !get_int(h, "NAXIS", &s.naxis) || !get_int(h, "NAXIS1", &s.naxis1) ||
-        !get_int(h, "NAXIS2", &s.naxis2) || !valid_structure(s))
-        return finish(out, fail(GCM_E_ARG, "primary HDU must be a 2-D image (BITPIX 8/16/32/64/-32/-64)"));
-    const uint64_t nd = data_bytes(s);
-    if (nd > fits_len || h.bytes > fits_len - nd)
-        return finish(out, fail(GCM_E_ARG, "FITS data shorter than NAXIS1 x NAXIS2 x |BITPIX|/8"));
+    GCM_ABI_TRY
+        if (!out)
+            return fail(GCM_E_ARG, "NULL result");
+        std::memset(out, 0, sizeof *out);
+        if (!ctx || !fits || !key_h || !key_d || !nonce_h || !nonce_d)
+            return finish(out, fail(GCM_E_ARG, "NULL argument"));
+        Header h;
+        if (!read_header(fits, fits_len, 0, &h) || h.cards[0].compare(0, 9, "SIMPLE  =") != 0)
+            return finish(out, fail(GCM_E_ARG, "input is not a FITS file with a complete primary header"));
+        Structure s;
+        if (!get_int(h, "BITPIX", &s.bitpix) || !get_int(h, "NAXIS", &s.naxis) || !get_int(h, "NAXIS1", &s.naxis1) ||
+            !get_int(h, "NAXIS2", &s.naxis2) || !valid_structure(s))
+            return finish(out, fail(GCM_E_ARG, "primary HDU must be a 2-D image (BITPIX 8/16/32/64/-32/-64)"));
+        const uint64_t nd = data_bytes(s);
+        if (nd > fits_len || h.bytes > fits_len - nd)
+            return finish(out, fail(GCM_E_ARG, "FITS data shorter than NAXIS1 x NAXIS2 x |BITPIX|/8"));
 
-    // header encrypted on the GPU (host pipeline); the HDU 0 cards need its tag
-    std::vector<uint8_t> ct_h(h.bytes);
-    uint8_t tag_h[16], tag_d[16];
-    int rc = gcm_encrypt_host(ctx, key_h, key_h_len, nonce_h, 12, nonce_h, 12, fits, h.bytes, ct_h.data(), tag_h);
-    if (rc)
-        return finish(out, rc);
-    // the HDU 0 and HDU 1 headers have fixed sizes (the tags are fixed-width
-    // hex), so the pixels are encrypted straight into their final place
-    const std::string enc = b64_encode(ct_h.data(), ct_h.size());
-    constexpr size_t kChunk = 64;
-    const size_t enc_cards = enc.empty() ? 1 : (enc.size() + kChunk - 1) / kChunk;
-    const size_t h0_bytes = pad_to_block((14 + enc_cards) * kCard), h1_bytes = kBlock;
-    rc = result_alloc(out, h0_bytes + h1_bytes + pad_to_block(nd));
-    if (rc)
-        return finish(out, rc);
-    uint8_t *blob = out->data + h0_bytes + h1_bytes;
-    {
-        const std::vector<uint8_t> aad = data_aad(nonce_d, s);
-        rc = gcm_encrypt_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), fits + h.bytes, nd, blob,
-                              tag_d);
-    }
-    if (rc) {
-        gcm_fits_free(out);
-        return finish(out, rc);
-    }
-    std::memset(blob + nd, 0, pad_to_block(nd) - nd);
+        // header encrypted on the GPU (host pipeline); the HDU 0 cards need its tag
+        std::vector<uint8_t> ct_h(h.bytes);
+        uint8_t tag_h[16], tag_d[16];
+        int rc = gcm_encrypt_host(ctx, key_h, key_h_len, nonce_h, 12, nonce_h, 12, fits, h.bytes, ct_h.data(), tag_h);
+        if (rc)
+            return finish(out, rc);
+        // the HDU 0 and HDU 1 headers have fixed sizes (the tags are fixed-width
+        // hex), so the pixels are encrypted straight into their final place
+        const std::string enc = b64_encode(ct_h.data(), ct_h.size());
+        constexpr size_t kChunk = 64;
+        const size_t enc_cards = enc.empty() ? 1 : (enc.size() + kChunk - 1) / kChunk;
+        const size_t h0_bytes = pad_to_block((14 + enc_cards) * kCard), h1_bytes = kBlock;
+        rc = result_alloc(out, h0_bytes + h1_bytes + pad_to_block(nd));
+        if (rc)
+            return finish(out, rc);
+        uint8_t *blob = out->data + h0_bytes + h1_bytes;
+        {
+            const std::vector<uint8_t> aad = data_aad(nonce_d, s);
+            rc = gcm_encrypt_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), fits + h.bytes, nd, blob,
+                                  tag_d);
+        }
+        if (rc) {
+            gcm_fits_free(out);
+            return finish(out, rc);
+        }
+        std::memset(blob + nd, 0, pad_to_block(nd) - nd);
 
-    std::vector<std::string> c0 = {card_logical("SIMPLE", true), card_int("BITPIX", 8), card_int("NAXIS", 0),
-                                   card_logical("EXTEND", true), card_str("LONGSTRN", "OGIP 1.0"),
-                                   card_str("NONCE_H", hex(nonce_h, 12)), card_str("NONCE_D", hex(nonce_d, 12)),
-                                   card_int("ORIG_BPX", s.bitpix), card_int("ORIG_NAX", s.naxis),
-                                   card_int("ORIG_NA1", s.naxis1), card_int("ORIG_NA2", s.naxis2),
-                                   card_hierarch_str("AUTHTAG_H", hex(tag_h, 16)),
-                                   card_hierarch_str("AUTHTAG_D", hex(tag_d, 16))};
-    for (size_t i = 0; i < enc.size() || i == 0; i += kChunk) {
-        const bool last = i + kChunk >= enc.size();
-        const std::string part = enc.substr(i, kChunk) + (last ? "" : "&");
-        c0.push_back(card_raw((i == 0 ? std::string("ENCHDR  = '") : std::string("CONTINUE  '")) + part + "'"));
-    }
-    c0.push_back(card_raw("END"));
-    std::vector<std::string> c1 = {card_str("XTENSION", "BINTABLE"), card_int("BITPIX", 8), card_int("NAXIS", 2),
-                                   card_int("NAXIS1", (long long)nd), card_int("NAXIS2", 1), card_int("PCOUNT", 0),
-                                   card_int("GCOUNT", 1), card_int("TFIELDS", 1), card_str("TTYPE1", "BLOB"),
-                                   card_str("TFORM1", std::to_string(nd) + "B"), card_raw("END")};
-    const std::vector<uint8_t> b0 = card_bytes(c0), b1 = card_bytes(c1);
-    if (b0.size() != h0_bytes || b1.size() != h1_bytes) {  // the fixed layout above must hold
-        gcm_fits_free(out);
-        return finish(out, fail(GCM_E_ARG, "internal: container header sizes %zu/%zu", b0.size(), b1.size()));
-    }
-    std::memcpy(out->data, b0.data(), h0_bytes);
-    std::memcpy(out->data + h0_bytes, b1.data(), h1_bytes);
-    out->warning_code = 0;
-    return finish(out, GCM_OK);
+        std::vector<std::string> c0 = {card_logical("SIMPLE", true), card_int("BITPIX", 8), card_int("NAXIS", 0),
+                                       card_logical("EXTEND", true), card_str("LONGSTRN", "OGIP 1.0"),
+                                       card_str("NONCE_H", hex(nonce_h, 12)), card_str("NONCE_D", hex(nonce_d, 12)),
+                                       card_int("ORIG_BPX", s.bitpix), card_int("ORIG_NAX", s.naxis),
+                                       card_int("ORIG_NA1", s.naxis1), card_int("ORIG_NA2", s.naxis2),
+                                       card_hierarch_str("AUTHTAG_H", hex(tag_h, 16)),
+                                       card_hierarch_str("AUTHTAG_D", hex(tag_d, 16))};
+        for (size_t i = 0; i < enc.size() || i == 0; i += kChunk) {
+            const bool last = i + kChunk >= enc.size();
+            const std::string part = enc.substr(i, kChunk) + (last ? "" : "&");
+            c0.push_back(card_raw((i == 0 ? std::string("ENCHDR  = '") : std::string("CONTINUE  '")) + part + "'"));
+        }
+        c0.push_back(card_raw("END"));
+        std::vector<std::string> c1 = {card_str("XTENSION", "BINTABLE"), card_int("BITPIX", 8), card_int("NAXIS", 2),
+                                       card_int("NAXIS1", (long long)nd), card_int("NAXIS2", 1), card_int("PCOUNT", 0),
+                                       card_int("GCOUNT", 1), card_int("TFIELDS", 1), card_str("TTYPE1", "BLOB"),
+                                       card_str("TFORM1", std::to_string(nd) + "B"), card_raw("END")};
+        const std::vector<uint8_t> b0 = card_bytes(c0), b1 = card_bytes(c1);
+        if (b0.size() != h0_bytes || b1.size() != h1_bytes) {  // the fixed layout above must hold
+            gcm_fits_free(out);
+            return finish(out, fail(GCM_E_ARG, "internal: container header sizes %zu/%zu", b0.size(), b1.size()));
+        }
+        std::memcpy(out->data, b0.data(), h0_bytes);
+        std::memcpy(out->data + h0_bytes, b1.data(), h1_bytes);
+        out->warning_code = 0;
+        return finish(out, GCM_OK);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_fits_decrypt(gcm_ctx *ctx, const uint8_t *container, uint64_t len, const uint8_t *key_h,
                                 size_t key_h_len, const uint8_t *key_d, size_t key_d_len, gcm_fits_result *out)
 {
-    if (!out)
-        return fail(GCM_E_ARG, "NULL result");
-    std::memset(out, 0, sizeof *out);
-    if (!ctx || !container)
-        return finish(out, fail(GCM_E_ARG, "NULL argument"));
-    Header h0, h1;
-    Structure s;
-    std::string nh, nd_hex, th, td, enc;
-    uint8_t nonce_h[12], nonce_d[12], tag_h[16], tag_d[16];
-    if (!read_header(container, len, 0, &h0) || !read_header(container, len, h0.bytes, &h1) ||
-        !get_int(h0, "ORIG_BPX", &s.bitpix) || !get_int(h0, "ORIG_NAX", &s.naxis) ||
-        !get_int(h0, "ORIG_NA1", &s.naxis1) || !get_int(h0, "ORIG_NA2", &s.naxis2) || !valid_structure(s) ||
-        !get_str(h0, "NONCE_H", &nh) || !get_str(h0, "NONCE_D", &nd_hex) || !unhex(nh, nonce_h, 12) ||
-        !unhex(nd_hex, nonce_d, 12) || !get_hierarch_str(h0, "AUTHTAG_H", &th) ||
-        !get_hierarch_str(h0, "AUTHTAG_D", &td) || !unhex(th, tag_h, 16) || !unhex(td, tag_d, 16) ||
-        !get_long_str(h0, "ENCHDR", &enc))
-        return finish(out, fail(GCM_E_ARG, "not an authenticated FITS container"));
-    // the blob: N bytes as the BINTABLE declares them
-    long long nblob = -1;
-    std::string tform;
-    if (!get_int(h1, "NAXIS1", &nblob) || nblob < 0 || (uint64_t)nblob > len || !get_str(h1, "TFORM1", &tform) ||
-        tform != std::to_string(nblob) + "B" || h0.bytes + h1.bytes > len - (uint64_t)nblob)
-        return finish(out, fail(GCM_E_ARG, "container blob is not a %lld-byte TFORM1 cell", nblob));
-    std::vector<uint8_t> ct_h;
-    if (!b64_decode(enc, &ct_h) || ct_h.empty() || ct_h.size() % kBlock)
-        return finish(out, fail(GCM_E_ARG, "ENCHDR is not a base64 FITS header"));
-    const uint8_t *ct_d = container + h0.bytes + h1.bytes;
+    GCM_ABI_TRY
+        if (!out)
+            return fail(GCM_E_ARG, "NULL result");
+        std::memset(out, 0, sizeof *out);
+        if (!ctx || !container)
+            return finish(out, fail(GCM_E_ARG, "NULL argument"));
+        Header h0, h1;
+        Structure s;
+        std::string nh, nd_hex, th, td, enc;
+        uint8_t nonce_h[12], nonce_d[12], tag_h[16], tag_d[16];
+        if (!read_header(container, len, 0, &h0) || !read_header(container, len, h0.bytes, &h1) ||
+            !get_int(h0, "ORIG_BPX", &s.bitpix) || !get_int(h0, "ORIG_NAX", &s.naxis) ||
+            !get_int(h0, "ORIG_NA1", &s.naxis1) || !get_int(h0, "ORIG_NA2", &s.naxis2) || !valid_structure(s) ||
+            !get_str(h0, "NONCE_H", &nh) || !get_str(h0, "NONCE_D", &nd_hex) || !unhex(nh, nonce_h, 12) ||
+            !unhex(nd_hex, nonce_d, 12) || !get_hierarch_str(h0, "AUTHTAG_H", &th) ||
+            !get_hierarch_str(h0, "AUTHTAG_D", &td) || !unhex(th, tag_h, 16) || !unhex(td, tag_d, 16) ||
+            !get_long_str(h0, "ENCHDR", &enc))
+            return finish(out, fail(GCM_E_ARG, "not an authenticated FITS container"));
+        // the blob: N bytes as the BINTABLE declares them
+        long long nblob = -1;
+        std::string tform;
+        if (!get_int(h1, "NAXIS1", &nblob) || nblob < 0 || (uint64_t)nblob > len || !get_str(h1, "TFORM1", &tform) ||
+            tform != std::to_string(nblob) + "B" || h0.bytes + h1.bytes > len - (uint64_t)nblob)
+            return finish(out, fail(GCM_E_ARG, "container blob is not a %lld-byte TFORM1 cell", nblob));
+        std::vector<uint8_t> ct_h;
+        if (!b64_decode(enc, &ct_h) || ct_h.empty() || ct_h.size() % kBlock)
+            return finish(out, fail(GCM_E_ARG, "ENCHDR is not a base64 FITS header"));
+        const uint8_t *ct_d = container + h0.bytes + h1.bytes;
 
-    int warn = 0;
-    // header: the authenticated original, else a minimal header from ORIG_*;
-    // the output pixels take the shape of whichever header is returned
-    std::vector<uint8_t> header(ct_h.size());
-    int ok_h = 0;
-    if (key_h) {
-        int rc = gcm_decrypt_verify_host(ctx, key_h, key_h_len, nonce_h, 12, nonce_h, 12, ct_h.data(), ct_h.size(),
-                                         tag_h, header.data(), &ok_h);
-        if (rc && rc != GCM_E_KEYLEN)
-            return finish(out, rc);
-        if (rc == GCM_E_KEYLEN)
-            ok_h = 0;
-    }
-    Structure so = s;
-    if (ok_h) {
-        Header ho;
-        if (!read_header(header.data(), header.size(), 0, &ho) || !get_int(ho, "BITPIX", &so.bitpix) ||
-            !get_int(ho, "NAXIS", &so.naxis) || !get_int(ho, "NAXIS1", &so.naxis1) ||
-            !get_int(ho, "NAXIS2", &so.naxis2) || !valid_structure(so))
-            return finish(out, fail(GCM_E_ARG, "authenticated header is not a 2-D image header"));
-        header.resize(ho.bytes);
-    } else {
-        header.clear();
-        append_cards(&header, {card_logical("SIMPLE", true), card_int("BITPIX", s.bitpix), card_int("NAXIS", s.naxis),
-                               card_int("NAXIS1", s.naxis1), card_int("NAXIS2", s.naxis2), card_raw("END")});
-        warn |= 1;
-    }
-    const uint64_t nout = data_bytes(so);
-    const size_t d0 = header.size();
-    int rc = result_alloc(out, d0 + pad_to_block(nout));
-    if (rc)
-        return finish(out, rc);
-    std::memcpy(out->data, header.data(), d0);
-    uint8_t *pix = out->data + d0;
-    // pixels: authenticated plaintext, else zeros (payload suppression); a blob
-    // whose size differs from the output shape cannot authenticate
-    int ok_d = 0;
-    if (key_d && (uint64_t)nblob == nout) {
-        const std::vector<uint8_t> aad = data_aad(nonce_d, s);
-        rc = gcm_decrypt_verify_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), ct_d, nout, tag_d,
-                                     pix, &ok_d);
-        if (rc && rc != GCM_E_KEYLEN) {
-            gcm_fits_free(out);
-            return finish(out, rc);
+        int warn = 0;
+        // header: the authenticated original, else a minimal header from ORIG_*;
+        // the output pixels take the shape of whichever header is returned
+        std::vector<uint8_t> header(ct_h.size());
+        int ok_h = 0;
+        if (key_h) {
+            int rc = gcm_decrypt_verify_host(ctx, key_h, key_h_len, nonce_h, 12, nonce_h, 12, ct_h.data(), ct_h.size(),
+                                             tag_h, header.data(), &ok_h);
+            if (rc && rc != GCM_E_KEYLEN)
+                return finish(out, rc);
+            if (rc == GCM_E_KEYLEN)
+                ok_h = 0;
         }
-        if (rc == GCM_E_KEYLEN)
-            ok_d = 0;
-    }
-    if (!ok_d) {
-        std::memset(pix, 0, nout);
-        warn |= 2;
-    }
-    std::memset(pix + nout, 0, pad_to_block(nout) - nout);
-    out->warning_code = warn;
-    return finish(out, GCM_OK);
+        Structure so = s;
+        if (ok_h) {
+            Header ho;
+            if (!read_header(header.data(), header.size(), 0, &ho) || !get_int(ho, "BITPIX", &so.bitpix) ||
+                !get_int(ho, "NAXIS", &so.naxis) || !get_int(ho, "NAXIS1", &so.naxis1) ||
+                !get_int(ho, "NAXIS2", &so.naxis2) || !valid_structure(so))
+                return finish(out, fail(GCM_E_ARG, "authenticated header is not a 2-D image header"));
+            header.resize(ho.bytes);
+        } else {
+            header.clear();
+            append_cards(&header, {card_logical("SIMPLE", true), card_int("BITPIX", s.bitpix), card_int("NAXIS", s.naxis),
+                                   card_int("NAXIS1", s.naxis1), card_int("NAXIS2", s.naxis2), card_raw("END")});
+            warn |= 1;
+        }
+        const uint64_t nout = data_bytes(so);
+        const size_t d0 = header.size();
+        int rc = result_alloc(out, d0 + pad_to_block(nout));
+        if (rc)
+            return finish(out, rc);
+        std::memcpy(out->data, header.data(), d0);
+        uint8_t *pix = out->data + d0;
+        // pixels: authenticated plaintext, else zeros (payload suppression); a blob
+        // whose size differs from the output shape cannot authenticate
+        int ok_d = 0;
+        if (key_d && (uint64_t)nblob == nout) {
+            const std::vector<uint8_t> aad = data_aad(nonce_d, s);
+            rc = gcm_decrypt_verify_host(ctx, key_d, key_d_len, nonce_d, 12, aad.data(), aad.size(), ct_d, nout, tag_d,
+                                         pix, &ok_d);
+            if (rc && rc != GCM_E_KEYLEN) {
+                gcm_fits_free(out);
+                return finish(out, rc);
+            }
+            if (rc == GCM_E_KEYLEN)
+                ok_d = 0;
+        }
+        if (!ok_d) {
+            std::memset(pix, 0, nout);
+            warn |= 2;
+        }
+        std::memset(pix + nout, 0, pad_to_block(nout) - nout);
+        out->warning_code = warn;
+        return finish(out, GCM_OK);
+    GCM_ABI_CATCH
 }

@@ -53,6 +53,30 @@ struct gcm_ctx {
     std::mutex mu;
 };
 
+// Every extern "C" entry point runs its body between GCM_ABI_TRY and one of
+// the GCM_ABI_CATCH forms, so that no C++ exception (a failed host
+// allocation, a thread that cannot be started) crosses the C boundary.
+#define GCM_ABI_TRY try {
+#define GCM_ABI_CATCH                     \
+    }                                     \
+    catch (...)                           \
+    {                                     \
+        return gcm::abi_exception();      \
+    }
+#define GCM_ABI_CATCH_VALUE(v)            \
+    }                                     \
+    catch (...)                           \
+    {                                     \
+        (void)gcm::abi_exception();       \
+        return (v);                       \
+    }
+#define GCM_ABI_CATCH_VOID                \
+    }                                     \
+    catch (...)                           \
+    {                                     \
+        (void)gcm::abi_exception();       \
+    }
+
 namespace gcm {
 
 constexpr uint64_t kMaxLen = (1ull << 36) - 32;  // 2^39 - 256 bits
@@ -60,6 +84,10 @@ constexpr uint64_t kMaxAad = (1ull << 61) - 1;   // < 2^64 bits
 
 int fail(int code, const char *fmt, ...);
 int fail_hip(hipError_t e, const char *what);
+// The status for the exception in flight (called from a catch block):
+// std::bad_alloc -> GCM_E_NOMEM, anything else -> GCM_E_INTERNAL, with the
+// message recorded for gcm_last_error.
+int abi_exception() noexcept;
 
 int ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes);
 void ctx_free(gcm_ctx *ctx, void *p, uint64_t bytes);

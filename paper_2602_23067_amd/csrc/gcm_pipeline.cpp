@@ -251,26 +251,32 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
 
 extern "C" int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes)
 {
-    if (!ctx)
-        return fail(GCM_E_ARG, "gcm_set_pipeline: NULL context");
-    if (chunk_bytes && (chunk_bytes < 4096 || chunk_bytes > (1ull << 34)))
-        return fail(GCM_E_ARG, "gcm_set_pipeline: chunk_bytes must be 0 or 4 KiB..16 GiB");
-    std::lock_guard<std::mutex> g(ctx->mu);
-    ctx->pipe_chunk = chunk_bytes;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_set_pipeline: NULL context");
+        if (chunk_bytes && (chunk_bytes < 4096 || chunk_bytes > (1ull << 34)))
+            return fail(GCM_E_ARG, "gcm_set_pipeline: chunk_bytes must be 0 or 4 KiB..16 GiB");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->pipe_chunk = chunk_bytes;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_encrypt_host(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv, size_t iv_len,
                                 const uint8_t *aad_h, uint64_t aad_len, const uint8_t *pt_h, uint64_t len,
                                 uint8_t *ct_h, uint8_t tag_out[16])
 {
-    return run_pipeline(ctx, 0, key, key_len, iv, iv_len, aad_h, aad_len, pt_h, len, ct_h, nullptr, tag_out,
-                        nullptr);
+    GCM_ABI_TRY
+        return run_pipeline(ctx, 0, key, key_len, iv, iv_len, aad_h, aad_len, pt_h, len, ct_h, nullptr, tag_out,
+                            nullptr);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_decrypt_verify_host(gcm_ctx *ctx, const uint8_t *key, size_t key_len, const uint8_t *iv,
                                        size_t iv_len, const uint8_t *aad_h, uint64_t aad_len, const uint8_t *ct_h,
                                        uint64_t len, const uint8_t tag[16], uint8_t *pt_h, int *accept)
 {
-    return run_pipeline(ctx, 1, key, key_len, iv, iv_len, aad_h, aad_len, ct_h, len, pt_h, tag, nullptr, accept);
+    GCM_ABI_TRY
+        return run_pipeline(ctx, 1, key, key_len, iv, iv_len, aad_h, aad_len, ct_h, len, pt_h, tag, nullptr, accept);
+    GCM_ABI_CATCH
 }

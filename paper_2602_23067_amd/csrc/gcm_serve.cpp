@@ -207,10 +207,8 @@ static void retire(gcm_serve *s, Slot &sl)
     sl.ids.clear();
 }
 
-static void worker_main(gcm_serve *s)
+static void worker_loop(gcm_serve *s, std::unique_lock<std::mutex> &lk)
 {
-    (void)hipSetDevice(s->ctx->device);
-    std::unique_lock<std::mutex> lk(s->mu);
     std::vector<PolicyReq> batch;
     std::vector<uint64_t> admitted;
     for (;;) {
@@ -271,107 +269,141 @@ static void worker_main(gcm_serve *s)
     }
 }
 
+// The scheduler thread.  If its host bookkeeping throws (a failed
+// allocation), it waits for the batches already on the GPU, completes every
+// request not yet done as rejected, records the error (new submissions then
+// fail with it) and ends, so that waiters return and stop can join.
+static void worker_main(gcm_serve *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    try {
+        worker_loop(s, lk);
+    } catch (...) {
+        if (!lk.owns_lock())
+            lk.lock();
+        s->worker_error = abi_exception();
+        const int64_t t = now_ns();
+        for (Slot &sl : s->slots)
+            if (sl.busy) {
+                (void)hipEventSynchronize(sl.done);
+                sl.busy = false;
+            }
+        for (auto &kv : s->reqs)
+            if (kv.second.state != 2) {
+                kv.second.state = 2;
+                kv.second.accept = 0;
+                kv.second.t_done = t;
+            }
+        s->cv_done.notify_all();
+    }
+}
+
 extern "C" int gcm_serve_start(gcm_ctx *ctx, const gcm_serve_config *cfg, gcm_serve **out)
 {
-    if (!ctx || !out)
-        return fail(GCM_E_ARG, "gcm_serve_start: NULL argument");
-    *out = nullptr;
-    gcm_serve_config c{};
-    c.n_streams = 4;
-    c.hbm_budget = 64ull << 30;
-    c.max_batch_reqs = 256;
-    c.max_batch_bytes = 256ull << 20;
-    c.max_queue = 1u << 16;
-    if (cfg) {
-        if (cfg->n_streams)
-            c.n_streams = cfg->n_streams;
-        if (cfg->hbm_budget)
-            c.hbm_budget = cfg->hbm_budget;
-        if (cfg->max_batch_reqs)
-            c.max_batch_reqs = cfg->max_batch_reqs;
-        if (cfg->max_batch_bytes)
-            c.max_batch_bytes = cfg->max_batch_bytes;
-        if (cfg->max_queue)
-            c.max_queue = cfg->max_queue;
-    }
-    if (c.n_streams > 16)
-        return fail(GCM_E_ARG, "gcm_serve_start: at most 16 streams");
-    gcm_serve *s = new (std::nothrow) gcm_serve();
-    if (!s)
-        return fail(GCM_E_NOMEM, "gcm_serve_start: host allocation failed");
-    s->ctx = ctx;
-    s->cfg = c;
-    PolicyConfig pc;
-    pc.budget = c.hbm_budget;
-    pc.max_batch_reqs = c.max_batch_reqs;
-    pc.max_batch_bytes = c.max_batch_bytes;
-    pc.max_queue = c.max_queue;
-    s->policy = ServePolicy(pc);
-    s->slots.resize(c.n_streams);
-    hipError_t e = hipSetDevice(ctx->device);
-    for (Slot &sl : s->slots) {
-        if (e == hipSuccess)
-            e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
-        if (e == hipSuccess)
-            e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
-    }
-    if (e != hipSuccess) {
-        for (Slot &sl : s->slots) {
-            if (sl.done)
-                (void)hipEventDestroy(sl.done);
-            if (sl.stream)
-                (void)hipStreamDestroy(sl.stream);
+    GCM_ABI_TRY
+        if (!ctx || !out)
+            return fail(GCM_E_ARG, "gcm_serve_start: NULL argument");
+        *out = nullptr;
+        gcm_serve_config c{};
+        c.n_streams = 4;
+        c.hbm_budget = 64ull << 30;
+        c.max_batch_reqs = 256;
+        c.max_batch_bytes = 256ull << 20;
+        c.max_queue = 1u << 16;
+        if (cfg) {
+            if (cfg->n_streams)
+                c.n_streams = cfg->n_streams;
+            if (cfg->hbm_budget)
+                c.hbm_budget = cfg->hbm_budget;
+            if (cfg->max_batch_reqs)
+                c.max_batch_reqs = cfg->max_batch_reqs;
+            if (cfg->max_batch_bytes)
+                c.max_batch_bytes = cfg->max_batch_bytes;
+            if (cfg->max_queue)
+                c.max_queue = cfg->max_queue;
         }
-        delete s;
-        return fail_hip(e, "serving stream creation");
-    }
-    s->worker = std::thread(worker_main, s);
-    *out = s;
-    return GCM_OK;
+        if (c.n_streams > 16)
+            return fail(GCM_E_ARG, "gcm_serve_start: at most 16 streams");
+        gcm_serve *s = new (std::nothrow) gcm_serve();
+        if (!s)
+            return fail(GCM_E_NOMEM, "gcm_serve_start: host allocation failed");
+        s->ctx = ctx;
+        s->cfg = c;
+        PolicyConfig pc;
+        pc.budget = c.hbm_budget;
+        pc.max_batch_reqs = c.max_batch_reqs;
+        pc.max_batch_bytes = c.max_batch_bytes;
+        pc.max_queue = c.max_queue;
+        s->policy = ServePolicy(pc);
+        s->slots.resize(c.n_streams);
+        hipError_t e = hipSetDevice(ctx->device);
+        for (Slot &sl : s->slots) {
+            if (e == hipSuccess)
+                e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            for (Slot &sl : s->slots) {
+                if (sl.done)
+                    (void)hipEventDestroy(sl.done);
+                if (sl.stream)
+                    (void)hipStreamDestroy(sl.stream);
+            }
+            delete s;
+            return fail_hip(e, "serving stream creation");
+        }
+        s->worker = std::thread(worker_main, s);
+        *out = s;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_serve_submit(gcm_serve *s, const gcm_request *req, uint64_t *id_out)
 {
-    if (!s || !req || !id_out)
-        return fail(GCM_E_ARG, "gcm_serve_submit: NULL argument");
-    const gcm_request &r = *req;
-    if (r.op > 1 || r.reserved)
-        return fail(GCM_E_ARG, "gcm_serve_submit: bad op or reserved field");
-    if (!r.tag_d)
-        return fail(GCM_E_ARG, "gcm_serve_submit: tag_d is required");
-    int rc = check_message(r.aad_len, r.len, r.aad_d, r.in_d, r.out_d);
-    if (rc)
-        return rc;
-    {
-        std::lock_guard<std::mutex> g(s->ctx->mu);
-        if (r.key_slot >= s->ctx->n_slots || !s->ctx->slot_used[r.key_slot])
-            return fail(GCM_E_SLOT, "key slot %u is not registered", r.key_slot);
-    }
-    const uint64_t need = r.len + (r.out_d != r.in_d ? r.len : 0) + r.aad_len;
-    std::lock_guard<std::mutex> g(s->mu);
-    if (s->stopping)
-        return fail(GCM_E_ARG, "gcm_serve_submit: server is stopping");
-    if (s->worker_error)
-        return fail(s->worker_error, "gcm_serve_submit: the serving loop hit an earlier error");
-    const uint64_t id = s->next_id;
-    const int o = s->policy.offer(PolicyReq{id, need, r.len});
-    if (o == ServePolicy::kTooLarge)
-        return fail(GCM_E_NOMEM, "request needs %llu bytes, more than the %llu-byte HBM budget",
-                    (unsigned long long)need, (unsigned long long)s->cfg.hbm_budget);
-    if (o == ServePolicy::kQueueFull)
-        return fail(GCM_E_BUSY, "serving queue is full");
-    s->next_id++;
-    ReqState st;
-    st.r = r;
-    st.need = need;
-    st.t_submit = now_ns();
-    if (!s->t_first)
-        s->t_first = st.t_submit;
-    s->reqs.emplace(id, st);
-    s->submitted++;
-    *id_out = id;
-    s->cv_work.notify_one();
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!s || !req || !id_out)
+            return fail(GCM_E_ARG, "gcm_serve_submit: NULL argument");
+        const gcm_request &r = *req;
+        if (r.op > 1 || r.reserved)
+            return fail(GCM_E_ARG, "gcm_serve_submit: bad op or reserved field");
+        if (!r.tag_d)
+            return fail(GCM_E_ARG, "gcm_serve_submit: tag_d is required");
+        int rc = check_message(r.aad_len, r.len, r.aad_d, r.in_d, r.out_d);
+        if (rc)
+            return rc;
+        {
+            std::lock_guard<std::mutex> g(s->ctx->mu);
+            if (r.key_slot >= s->ctx->n_slots || !s->ctx->slot_used[r.key_slot])
+                return fail(GCM_E_SLOT, "key slot %u is not registered", r.key_slot);
+        }
+        const uint64_t need = r.len + (r.out_d != r.in_d ? r.len : 0) + r.aad_len;
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stopping)
+            return fail(GCM_E_ARG, "gcm_serve_submit: server is stopping");
+        if (s->worker_error)
+            return fail(s->worker_error, "gcm_serve_submit: the serving loop hit an earlier error");
+        const uint64_t id = s->next_id;
+        const int o = s->policy.offer(PolicyReq{id, need, r.len});
+        if (o == ServePolicy::kTooLarge)
+            return fail(GCM_E_NOMEM, "request needs %llu bytes, more than the %llu-byte HBM budget",
+                        (unsigned long long)need, (unsigned long long)s->cfg.hbm_budget);
+        if (o == ServePolicy::kQueueFull)
+            return fail(GCM_E_BUSY, "serving queue is full");
+        s->next_id++;
+        ReqState st;
+        st.r = r;
+        st.need = need;
+        st.t_submit = now_ns();
+        if (!s->t_first)
+            s->t_first = st.t_submit;
+        s->reqs.emplace(id, st);
+        s->submitted++;
+        *id_out = id;
+        s->cv_work.notify_one();
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 static int report(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *latency_ns, bool consume)
@@ -395,39 +427,45 @@ static int report(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *l
 
 extern "C" int gcm_serve_poll(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *latency_ns)
 {
-    if (!s)
-        return fail(GCM_E_ARG, "gcm_serve_poll: NULL server");
-    std::lock_guard<std::mutex> g(s->mu);
-    return report(s, id, done, accept, latency_ns, true);
+    GCM_ABI_TRY
+        if (!s)
+            return fail(GCM_E_ARG, "gcm_serve_poll: NULL server");
+        std::lock_guard<std::mutex> g(s->mu);
+        return report(s, id, done, accept, latency_ns, true);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_serve_wait(gcm_serve *s, uint64_t id, int *accept, uint64_t *latency_ns)
 {
-    if (!s)
-        return fail(GCM_E_ARG, "gcm_serve_wait: NULL server");
-    std::unique_lock<std::mutex> lk(s->mu);
-    for (;;) {
-        auto it = s->reqs.find(id);
-        if (it == s->reqs.end())
-            return fail(GCM_E_ARG, "unknown or already collected request id %llu", (unsigned long long)id);
-        if (it->second.state == 2)
-            return report(s, id, nullptr, accept, latency_ns, true);
-        s->cv_done.wait(lk);
-    }
+    GCM_ABI_TRY
+        if (!s)
+            return fail(GCM_E_ARG, "gcm_serve_wait: NULL server");
+        std::unique_lock<std::mutex> lk(s->mu);
+        for (;;) {
+            auto it = s->reqs.find(id);
+            if (it == s->reqs.end())
+                return fail(GCM_E_ARG, "unknown or already collected request id %llu", (unsigned long long)id);
+            if (it->second.state == 2)
+                return report(s, id, nullptr, accept, latency_ns, true);
+            s->cv_done.wait(lk);
+        }
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_serve_drain(gcm_serve *s)
 {
-    if (!s)
-        return fail(GCM_E_ARG, "gcm_serve_drain: NULL server");
-    std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_done.wait(lk, [&] {
-        for (auto &kv : s->reqs)
-            if (kv.second.state != 2)
-                return false;
-        return true;
-    });
-    return s->worker_error;
+    GCM_ABI_TRY
+        if (!s)
+            return fail(GCM_E_ARG, "gcm_serve_drain: NULL server");
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_done.wait(lk, [&] {
+            for (auto &kv : s->reqs)
+                if (kv.second.state != 2)
+                    return false;
+            return true;
+        });
+        return s->worker_error;
+    GCM_ABI_CATCH
 }
 
 static double pct(std::vector<double> v, double q)
@@ -443,56 +481,60 @@ static double pct(std::vector<double> v, double q)
 
 extern "C" int gcm_serve_get_stats(gcm_serve *s, gcm_serve_stats *out)
 {
-    if (!s || !out)
-        return fail(GCM_E_ARG, "gcm_serve_get_stats: NULL argument");
-    std::lock_guard<std::mutex> g(s->mu);
-    std::memset(out, 0, sizeof *out);
-    out->submitted = s->submitted;
-    out->completed = s->completed;
-    out->rejected = s->rejected;
-    out->batches = s->batches;
-    out->bytes_completed = s->bytes_done;
-    out->budget_high_water = s->policy.high_water();
-    out->overlapped_admissions = s->overlapped_admissions;
-    out->max_inflight_batches = s->max_inflight;
-    out->p50_ms = pct(s->lat_ms, 0.50);
-    out->p99_ms = pct(s->lat_ms, 0.99);
-    out->max_ms = s->lat_ms.empty() ? 0.0 : *std::max_element(s->lat_ms.begin(), s->lat_ms.end());
-    double sum = 0;
-    for (double x : s->lat_ms)
-        sum += x;
-    out->mean_ms = s->lat_ms.empty() ? 0.0 : sum / (double)s->lat_ms.size();
-    out->wall_s = s->t_last > s->t_first ? (double)(s->t_last - s->t_first) * 1e-9 : 0.0;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!s || !out)
+            return fail(GCM_E_ARG, "gcm_serve_get_stats: NULL argument");
+        std::lock_guard<std::mutex> g(s->mu);
+        std::memset(out, 0, sizeof *out);
+        out->submitted = s->submitted;
+        out->completed = s->completed;
+        out->rejected = s->rejected;
+        out->batches = s->batches;
+        out->bytes_completed = s->bytes_done;
+        out->budget_high_water = s->policy.high_water();
+        out->overlapped_admissions = s->overlapped_admissions;
+        out->max_inflight_batches = s->max_inflight;
+        out->p50_ms = pct(s->lat_ms, 0.50);
+        out->p99_ms = pct(s->lat_ms, 0.99);
+        out->max_ms = s->lat_ms.empty() ? 0.0 : *std::max_element(s->lat_ms.begin(), s->lat_ms.end());
+        double sum = 0;
+        for (double x : s->lat_ms)
+            sum += x;
+        out->mean_ms = s->lat_ms.empty() ? 0.0 : sum / (double)s->lat_ms.size();
+        out->wall_s = s->t_last > s->t_first ? (double)(s->t_last - s->t_first) * 1e-9 : 0.0;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_serve_stop(gcm_serve *s)
 {
-    if (!s)
-        return fail(GCM_E_ARG, "gcm_serve_stop: NULL server");
-    {
-        std::lock_guard<std::mutex> g(s->mu);
-        s->stopping = true;
-    }
-    s->cv_work.notify_all();
-    if (s->worker.joinable())
-        s->worker.join();
-    const int err = s->worker_error;
-    (void)hipSetDevice(s->ctx->device);
-    for (Slot &sl : s->slots) {
-        if (sl.stream)
-            (void)hipStreamSynchronize(sl.stream);
+    GCM_ABI_TRY
+        if (!s)
+            return fail(GCM_E_ARG, "gcm_serve_stop: NULL server");
         {
-            std::lock_guard<std::mutex> g(s->ctx->mu);
-            ctx_free(s->ctx, sl.d_mem, sl.d_bytes);
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stopping = true;
         }
-        if (sl.h_mem)
-            (void)hipHostFree(sl.h_mem);
-        if (sl.done)
-            (void)hipEventDestroy(sl.done);
-        if (sl.stream)
-            (void)hipStreamDestroy(sl.stream);
-    }
-    delete s;
-    return err;
+        s->cv_work.notify_all();
+        if (s->worker.joinable())
+            s->worker.join();
+        const int err = s->worker_error;
+        (void)hipSetDevice(s->ctx->device);
+        for (Slot &sl : s->slots) {
+            if (sl.stream)
+                (void)hipStreamSynchronize(sl.stream);
+            {
+                std::lock_guard<std::mutex> g(s->ctx->mu);
+                ctx_free(s->ctx, sl.d_mem, sl.d_bytes);
+            }
+            if (sl.h_mem)
+                (void)hipHostFree(sl.h_mem);
+            if (sl.done)
+                (void)hipEventDestroy(sl.done);
+            if (sl.stream)
+                (void)hipStreamDestroy(sl.stream);
+        }
+        delete s;
+        return err;
+    GCM_ABI_CATCH
 }

@@ -133,12 +133,14 @@ int siv_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *nonce, s
 
 extern "C" uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len)
 {
-    if (!ctx)
-        return 0;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    uint32_t log2B, waves, gpc;
-    const uint64_t T = siv_tiles(ctx, len, aad_len, &log2B, &waves, &gpc);
-    return kSivTilesOff + workspace_bytes_for(T, 1);
+    GCM_ABI_TRY
+        if (!ctx)
+            return 0;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        uint32_t log2B, waves, gpc;
+        const uint64_t T = siv_tiles(ctx, len, aad_len, &log2B, &waves, &gpc);
+        return kSivTilesOff + workspace_bytes_for(T, 1);
+    GCM_ABI_CATCH_VALUE(0)
 }
 
 extern "C" int gcm_siv_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *nonce, size_t nonce_len,
@@ -146,8 +148,10 @@ extern "C" int gcm_siv_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t 
                                      uint8_t *ct_d, uint8_t *tag_d, void *workspace_d, uint64_t workspace_bytes,
                                      void *stream)
 {
-    return siv_common(ctx, 0, slot, nonce, nonce_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
-                      workspace_bytes, stream);
+    GCM_ABI_TRY
+        return siv_common(ctx, 0, slot, nonce, nonce_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
+                          workspace_bytes, stream);
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_siv_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *nonce, size_t nonce_len,
@@ -155,6 +159,8 @@ extern "C" int gcm_siv_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const u
                                             uint64_t len, const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d,
                                             void *workspace_d, uint64_t workspace_bytes, void *stream)
 {
-    return siv_common(ctx, 1, slot, nonce, nonce_len, aad_d, aad_len, ct_d, len, pt_d, const_cast<uint8_t *>(tag_d),
-                      accept_d, workspace_d, workspace_bytes, stream);
+    GCM_ABI_TRY
+        return siv_common(ctx, 1, slot, nonce, nonce_len, aad_d, aad_len, ct_d, len, pt_d, const_cast<uint8_t *>(tag_d),
+                          accept_d, workspace_d, workspace_bytes, stream);
+    GCM_ABI_CATCH
 }

@@ -92,147 +92,155 @@ static void segment_desc(const gcm_stream *st, MsgDesc *d)
 extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
                                 const uint8_t *aad_d, uint64_t aad_len, gcm_stream **out, void *stream)
 {
-    if (!ctx || !iv || !out)
-        return fail(GCM_E_ARG, "NULL argument");
-    *out = nullptr;
-    if (op > 1)
-        return fail(GCM_E_ARG, "op must be 0 (encrypt) or 1 (decrypt-verify)");
-    if (!valid_iv_len(iv_len))
-        return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
-    int rc = check_message(aad_len, 0, aad_d, nullptr, nullptr);
-    if (rc)
-        return rc;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> g(ctx->mu);
-    if (slot >= ctx->n_slots || !ctx->slot_used[slot])
-        return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-    gcm_stream *st = new (std::nothrow) gcm_stream();
-    if (!st)
-        return fail(GCM_E_NOMEM, "host allocation failed");
-    st->ctx = ctx;
-    st->op = op;
-    st->slot = slot;
-    st->nr = ctx->slot_nr[slot];
-    st->aad_len = aad_len;
-    rc = ctx_alloc(ctx, reinterpret_cast<void **>(&st->d_state), kStateBytes);
-    if (rc) {
-        delete st;
-        return rc;
-    }
-    // J0 (any IV length) and Y = 0
-    IvArg a;
-    std::memset(&a, 0, sizeof a);
-    a.len = (uint32_t)iv_len;
-    std::memcpy(a.b, iv, iv_len);
-    e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_state + 16, st->d_state, s);
-    if (e != hipSuccess)
-        rc = fail_hip(e, "J0 kernel launch");
-    if (rc == GCM_OK && aad_len) {
-        // segment 0: the AAD blocks, from Y = 0
-        MsgDesc d;
-        segment_desc(st, &d);
-        d.aad = (uint64_t)aad_d;
-        d.aad_len = aad_len;
-        d.na = (aad_len + 15) / 16;
-        d.n = 0;
-        d.m = d.na;
-        d.yout = (uint64_t)st->d_state;
-        rc = run_segment(st, d, s);
-    }
-    if (rc) {
-        (void)hipStreamSynchronize(s);
-        ctx_free(ctx, st->ws, st->ws_bytes);
-        ctx_free(ctx, st->d_state, kStateBytes);
-        delete st;
-        return rc;
-    }
-    *out = st;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!ctx || !iv || !out)
+            return fail(GCM_E_ARG, "NULL argument");
+        *out = nullptr;
+        if (op > 1)
+            return fail(GCM_E_ARG, "op must be 0 (encrypt) or 1 (decrypt-verify)");
+        if (!valid_iv_len(iv_len))
+            return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
+        int rc = check_message(aad_len, 0, aad_d, nullptr, nullptr);
+        if (rc)
+            return rc;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (slot >= ctx->n_slots || !ctx->slot_used[slot])
+            return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipSetDevice");
+        gcm_stream *st = new (std::nothrow) gcm_stream();
+        if (!st)
+            return fail(GCM_E_NOMEM, "host allocation failed");
+        st->ctx = ctx;
+        st->op = op;
+        st->slot = slot;
+        st->nr = ctx->slot_nr[slot];
+        st->aad_len = aad_len;
+        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&st->d_state), kStateBytes);
+        if (rc) {
+            delete st;
+            return rc;
+        }
+        // J0 (any IV length) and Y = 0
+        IvArg a;
+        std::memset(&a, 0, sizeof a);
+        a.len = (uint32_t)iv_len;
+        std::memcpy(a.b, iv, iv_len);
+        e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_state + 16, st->d_state, s);
+        if (e != hipSuccess)
+            rc = fail_hip(e, "J0 kernel launch");
+        if (rc == GCM_OK && aad_len) {
+            // segment 0: the AAD blocks, from Y = 0
+            MsgDesc d;
+            segment_desc(st, &d);
+            d.aad = (uint64_t)aad_d;
+            d.aad_len = aad_len;
+            d.na = (aad_len + 15) / 16;
+            d.n = 0;
+            d.m = d.na;
+            d.yout = (uint64_t)st->d_state;
+            rc = run_segment(st, d, s);
+        }
+        if (rc) {
+            (void)hipStreamSynchronize(s);
+            ctx_free(ctx, st->ws, st->ws_bytes);
+            ctx_free(ctx, st->d_state, kStateBytes);
+            delete st;
+            return rc;
+        }
+        *out = st;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_stream_update(gcm_stream *st, const uint8_t *in_d, uint64_t len, uint8_t *out_d, void *stream)
 {
-    if (!st)
-        return fail(GCM_E_ARG, "NULL stream");
-    if (st->closed)
-        return fail(GCM_E_ARG, "gcm_stream_update after gcm_stream_final");
-    if (len == 0)
+    GCM_ABI_TRY
+        if (!st)
+            return fail(GCM_E_ARG, "NULL stream");
+        if (st->closed)
+            return fail(GCM_E_ARG, "gcm_stream_update after gcm_stream_final");
+        if (len == 0)
+            return GCM_OK;
+        if (st->tail)
+            return fail(GCM_E_ARG, "only the last segment may end inside a 16-byte block");
+        if (st->len + len > kMaxLen || st->len + len < st->len)
+            return fail(GCM_E_TOOLONG, "streamed length beyond the SP 800-38D limit");
+        int rc = check_message(0, len, nullptr, in_d, out_d);
+        if (rc)
+            return rc;
+        gcm_ctx *ctx = st->ctx;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipSetDevice");
+        MsgDesc d;
+        segment_desc(st, &d);
+        d.in = (uint64_t)in_d;
+        d.out = (uint64_t)out_d;
+        d.len = len;
+        d.na = 0;
+        d.n = (len + 15) / 16;
+        d.m = d.n;
+        d.ctr_off = (uint32_t)(st->len / 16);  // counters continue mod 2^32
+        d.ystate = (uint64_t)st->d_state;
+        d.yout = (uint64_t)st->d_state;
+        rc = run_segment(st, d, s);
+        if (rc)
+            return rc;
+        st->len += len;
+        st->tail = (len & 15) != 0;
         return GCM_OK;
-    if (st->tail)
-        return fail(GCM_E_ARG, "only the last segment may end inside a 16-byte block");
-    if (st->len + len > kMaxLen || st->len + len < st->len)
-        return fail(GCM_E_TOOLONG, "streamed length beyond the SP 800-38D limit");
-    int rc = check_message(0, len, nullptr, in_d, out_d);
-    if (rc)
-        return rc;
-    gcm_ctx *ctx = st->ctx;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-    MsgDesc d;
-    segment_desc(st, &d);
-    d.in = (uint64_t)in_d;
-    d.out = (uint64_t)out_d;
-    d.len = len;
-    d.na = 0;
-    d.n = (len + 15) / 16;
-    d.m = d.n;
-    d.ctr_off = (uint32_t)(st->len / 16);  // counters continue mod 2^32
-    d.ystate = (uint64_t)st->d_state;
-    d.yout = (uint64_t)st->d_state;
-    rc = run_segment(st, d, s);
-    if (rc)
-        return rc;
-    st->len += len;
-    st->tail = (len & 15) != 0;
-    return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_d, void *stream)
 {
-    if (!st || !tag_d || (st->op == 1 && !accept_d))
-        return fail(GCM_E_ARG, "NULL argument");
-    if (st->closed)
-        return fail(GCM_E_ARG, "gcm_stream_final called twice");
-    gcm_ctx *ctx = st->ctx;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    std::lock_guard<std::mutex> g(ctx->mu);
-    hipError_t e = hipSetDevice(ctx->device);
-    if (e != hipSuccess)
-        return fail_hip(e, "hipSetDevice");
-    // the length block alone: S = (Y ^ [8|A|]_64 || [8|C|]_64) * H, tag = S ^ E_K(J0)
-    MsgDesc d;
-    segment_desc(st, &d);
-    d.aad_len = st->aad_len;
-    d.len = st->len;
-    d.na = 0;
-    d.n = 0;
-    d.m = 1;
-    d.ystate = (uint64_t)st->d_state;
-    d.tag = (uint64_t)tag_d;
-    d.ok = (uint64_t)accept_d;
-    int rc = run_segment(st, d, s);
-    if (rc)
-        return rc;
-    st->closed = true;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!st || !tag_d || (st->op == 1 && !accept_d))
+            return fail(GCM_E_ARG, "NULL argument");
+        if (st->closed)
+            return fail(GCM_E_ARG, "gcm_stream_final called twice");
+        gcm_ctx *ctx = st->ctx;
+        hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        hipError_t e = hipSetDevice(ctx->device);
+        if (e != hipSuccess)
+            return fail_hip(e, "hipSetDevice");
+        // the length block alone: S = (Y ^ [8|A|]_64 || [8|C|]_64) * H, tag = S ^ E_K(J0)
+        MsgDesc d;
+        segment_desc(st, &d);
+        d.aad_len = st->aad_len;
+        d.len = st->len;
+        d.na = 0;
+        d.n = 0;
+        d.m = 1;
+        d.ystate = (uint64_t)st->d_state;
+        d.tag = (uint64_t)tag_d;
+        d.ok = (uint64_t)accept_d;
+        int rc = run_segment(st, d, s);
+        if (rc)
+            return rc;
+        st->closed = true;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }
 
 extern "C" int gcm_stream_destroy(gcm_stream *st)
 {
-    if (!st)
-        return fail(GCM_E_ARG, "NULL stream");
-    gcm_ctx *ctx = st->ctx;
-    std::lock_guard<std::mutex> g(ctx->mu);
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();  // the stream's queued segments may still read its state
-    ctx_free(ctx, st->ws, st->ws_bytes);
-    ctx_free(ctx, st->d_state, kStateBytes);
-    delete st;
-    return GCM_OK;
+    GCM_ABI_TRY
+        if (!st)
+            return fail(GCM_E_ARG, "NULL stream");
+        gcm_ctx *ctx = st->ctx;
+        std::lock_guard<std::mutex> g(ctx->mu);
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();  // the stream's queued segments may still read its state
+        ctx_free(ctx, st->ws, st->ws_bytes);
+        ctx_free(ctx, st->d_state, kStateBytes);
+        delete st;
+        return GCM_OK;
+    GCM_ABI_CATCH
 }

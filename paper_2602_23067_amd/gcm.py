@@ -24,6 +24,7 @@ GCM_E_HIP = -6
 GCM_E_BUSY = -7
 GCM_E_ALIAS = -8
 GCM_E_SLOT = -9
+GCM_E_INTERNAL = -10
 
 _lib: Optional[ctypes.CDLL] = None
 

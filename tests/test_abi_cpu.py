@@ -57,3 +57,27 @@ def test_last_error_is_a_string_before_any_call():
     if not os.path.exists(gcm.LIB_PATH):
         pytest.skip("library not built")
     assert isinstance(gcm.load().gcm_last_error(), bytes)
+
+
+def test_every_entry_point_contains_exceptions():
+    """No C++ exception may cross the C ABI: every multi-line extern "C"
+    function in the runtime runs its body between GCM_ABI_TRY and a
+    GCM_ABI_CATCH form (one-line accessors excepted)."""
+    src_dir = os.path.join(ROOT, "paper_2602_23067_amd", "csrc")
+    checked = 0
+    for path in sorted(glob.glob(os.path.join(src_dir, "*.cpp"))):
+        lines = open(path).read().split("\n")
+        for i, line in enumerate(lines):
+            if not line.startswith('extern "C"') or line.rstrip().endswith("}"):
+                continue
+            j = i
+            while lines[j] != "{":
+                j += 1
+            k = j
+            while lines[k] != "}":
+                k += 1
+            name = re.search(r"(gcm_\w+)\(", line).group(1)
+            assert lines[j + 1].strip() == "GCM_ABI_TRY", (path, name)
+            assert lines[k - 1].strip().startswith("GCM_ABI_CATCH"), (path, name)
+            checked += 1
+    assert checked >= 40

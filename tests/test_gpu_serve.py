@@ -1,8 +1,8 @@
 """GPU tests of the continuous-batching serving loop.
 
 Requests of mixed sizes, operations and resident keys arrive from another
-thread with exponential gaps while earlier batches run; every result is
-checked bit for bit against the CPU oracle (so it equals the same request
+thread in bursts, with exponential gaps between bursts, while earlier
+batches run; every result is checked bit for bit against the CPU oracle (so it equals the same request
 run alone), tampered decrypts are rejected and zero-filled, the admitted
 bytes never exceed the HBM budget, and requests were admitted while other
 batches were on the GPU."""
@@ -68,13 +68,18 @@ def test_serving_mixed_requests_match_oracle(ctx):
     budget = 3 << 20
     srv = gcm.Server(ctx, n_streams=4, hbm_budget=budget, max_batch_reqs=16, max_batch_bytes=512 << 10)
     ids = [None] * len(reqs)
-    gaps = workloads.rng_for(1, 56).exponential(200e-6, len(reqs))
+    # bursts of 8 back-to-back submissions with exponential gaps between
+    # bursts: inside a burst, later requests arrive while the burst's first
+    # batch is on the GPU (a sleep cannot be shorter than one small batch's
+    # ~50 us, so single submissions with short gaps do not reliably overlap)
+    gaps = workloads.rng_for(1, 56).exponential(500e-6, len(reqs))
 
     def submitter():
         for i, q in enumerate(reqs):
             a, x, y, t = bufs[i]
             ids[i] = srv.submit(q["op"], slots[q["k"]], q["iv"], a, x, y, t)
-            time.sleep(float(gaps[i]))
+            if i % 8 == 7:
+                time.sleep(float(gaps[i]))
 
     th = threading.Thread(target=submitter)
     th.start()
