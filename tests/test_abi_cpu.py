@@ -81,3 +81,20 @@ def test_every_entry_point_contains_exceptions():
             assert lines[k - 1].strip().startswith("GCM_ABI_CATCH"), (path, name)
             checked += 1
     assert checked >= 40
+
+
+def test_header_is_plain_c(tmp_path):
+    """The boundary header compiles as strict C99 and as C++ (no torch or
+    HIP types in any signature), and a C program can take every entry
+    point's address through it."""
+    import subprocess
+    hdr = os.path.join(ROOT, "include", "gcm_mi355.h")
+    names = sorted(_declared())
+    prog = tmp_path / "uses_header.c"
+    prog.write_text('#include "gcm_mi355.h"\n'
+                    "typedef void (*fn)(void);\n"
+                    "const fn entry_points[] = {\n" + ",\n".join(f"    (fn)&{n}" for n in names) + "\n};\n")
+    inc = os.path.dirname(hdr)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
+                    "-I", inc, str(prog)], check=True)
+    subprocess.run(["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", hdr], check=True)
