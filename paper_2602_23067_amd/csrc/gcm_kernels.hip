@@ -8,11 +8,18 @@
 //                                the fixed-multiplier GHASH tables.
 //   k_gcm_tiles                  per wave tile: AES-CTR + XOR + store, and a
 //                                per-lane Horner over the ciphertext with the
-//                                fixed multiplier H^64, then a log-depth
-//                                in-wave combine -> one 16-byte partial.
+//                                fixed multiplier H^64, then a per-lane
+//                                fix-up product and an XOR across the wave
+//                                -> one 16-byte partial.
 //   k_gcm_combine                per message: tree over the tile partials,
 //                                final *H, xor E_K(J0) -> tag / accept flag.
 //   k_gcm_zerofill               zero the output of every rejected message.
+//
+// AES-GCM-SIV (RFC 8452) reuses the same machinery: k_siv_derive builds a
+// per-message key slot from the key-generating key and the nonce,
+// k_siv_tiles runs POLYVAL (as GHASH over byte-reversed blocks), counter
+// mode with the little-endian counter, or both fused, and k_siv_tag forms or
+// checks the tag.
 //
 // No MFMA: the work is byte lookups and XORs, not a real-valued contraction.
 #include <hip/hip_runtime.h>
@@ -1337,7 +1344,8 @@ __global__ __launch_bounds__(64) void k_siv_derive(uint64_t kgk, SivArg na, uint
         for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
             rkw[i] = kh->rk[i];
         uint32_t half[12];
-        for (int i = 0; i < 6; ++i) {
+        const int nblk = k128 ? 4 : 6;
+        for (int i = 0; i < nblk; ++i) {
             const uint32_t in[4] = {(uint32_t)i, na.nonce[0], na.nonce[1], na.nonce[2]};
             uint32_t o[4];
             if (k128)
