@@ -72,7 +72,7 @@ typedef struct gcm_ctx gcm_ctx;
  *     allocate for key slots and scratch (0 = no bound).
  *   key_slots: number of resident key slots (each holds the round keys, H,
  *     the H^(2^k) power table and the GHASH multiplication tables, about
- *     387 KiB; the paper's precomputed table of powers of H).
+ *     403 KiB; the paper's precomputed table of powers of H).
  * Builds the AES tables on the device.  *out receives the context. */
 int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_bytes, uint32_t key_slots);
 
@@ -313,7 +313,7 @@ int gcm_fits_nonce(uint8_t out[12]);
  * identical or disjoint; the tag may sit anywhere in device memory.
  *
  * Device scratch for a message of `len` data and `aad_len` AAD bytes: a key
- * slot for the derived keys (about 387 KiB), the POLYVAL value and counter
+ * slot for the derived keys (about 403 KiB), the POLYVAL value and counter
  * block, and the per-tile partial hashes.  A workspace may be reused by calls
  * that are ordered on one stream. */
 uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);

@@ -36,9 +36,14 @@ constexpr uint64_t kTab8Bytes = 16ull * 256 * 16;             // byte-position t
 constexpr uint64_t kTab4Bytes = 32ull * 16 * 16;              // nibble-position table, 8 KiB
 constexpr uint64_t kSlotTab8Off = kSlotHdrBytes;
 constexpr uint64_t kSlotTab4Off = kSlotTab8Off + kTab8Bytes;
-constexpr uint64_t kSlotLanePowOff = kSlotTab4Off + kTab4Levels * kTab4Bytes;  // H^e, e = 0..63 (tile fix-ups)
+// Tile fix-up tables: lane l of a wave multiplies its Horner value by
+// c_l = H^(63 - l); entry (v, l) = (v * c_l) mod P for the 4-bit polynomial v
+// sits at byte 16 * (64 * v + l), as polynomial-order words (bit i of the
+// 128-bit value is the coefficient of x^i), 16 KiB in all.
+constexpr uint64_t kSlotLaneWinOff = kSlotTab4Off + kTab4Levels * kTab4Bytes;
 constexpr int kLanePows = 64;
-constexpr uint64_t kSlotBytes = kSlotLanePowOff + kLanePows * 16;
+constexpr uint64_t kLaneWinBytes = 16ull * kLanePows * 16;
+constexpr uint64_t kSlotBytes = kSlotLaneWinOff + kLaneWinBytes;
 static_assert(sizeof(KeySlotHdr) <= kSlotHdrBytes, "slot header too large");
 
 // ---- per-message descriptor ----

@@ -460,7 +460,8 @@ __device__ u32x4 gf_mul_wave(u32x4 a, u32x4 b)
 // Fixed-multiplier tables of one key (grid.y indexes the key).
 //   blocks 0..39:   nibble-position table of H^(2^b)      (fix-ups, combine tree)
 //   block 40:       byte-position table of H^64           (per-lane Horner multiplier)
-//   blocks 41..104: nibble-position table of H^e, e = 0..63 (per-lane tile fix-up)
+//   blocks 41..104: H^e, e = 0..63, and its 4-bit window table for the lane
+//                   l = 63 - e that multiplies by it in the tile fix-up
 __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
 {
     __shared__ u32x4 basis[128];  // basis[i] = M * x^i, memory order
@@ -475,16 +476,29 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
             m_sh = u32x4{hd->hpow[lvl][0], hd->hpow[lvl][1], hd->hpow[lvl][2], hd->hpow[lvl][3]};
         }
     } else {
-        // H^e as the product of H^(2^k) over the set bits of e (one wave);
-        // the tile fix-ups multiply by it in registers, so no table is built
+        // H^e as the product of H^(2^k) over the set bits of e (one wave),
+        // then thread v < 16 writes (v * H^e) mod P for lane 63 - e
         if (tid < 64) {
             const int e = b - kTab4Levels - 1;
             u32x4 m = {0x80u, 0u, 0u, 0u};  // the field's one
             for (int k = 0; k < 6; ++k)
                 if ((e >> k) & 1)
                     m = gf_mul_wave(m, u32x4{hd->hpow[k][0], hd->hpow[k][1], hd->hpow[k][2], hd->hpow[k][3]});
-            if (tid == 0)
-                reinterpret_cast<u32x4 *>(slot + kSlotLanePowOff)[e] = m;
+            if (tid < 16) {
+                const uint32_t mm[4] = {m.x, m.y, m.z, m.w};
+                const P128 pm = mem_to_poly(mm);
+                P128 t;
+                t.lo = 0;
+                t.hi = 0;
+                for (int i = 0; i < 4; ++i)
+                    if ((tid >> i) & 1) {
+                        const P128 sh = poly_mul_xi(pm, i);
+                        t.lo ^= sh.lo;
+                        t.hi ^= sh.hi;
+                    }
+                reinterpret_cast<u32x4 *>(slot + kSlotLaneWinOff)[kLanePows * tid + (63 - e)] =
+                    u32x4{(uint32_t)t.lo, (uint32_t)(t.lo >> 32), (uint32_t)t.hi, (uint32_t)(t.hi >> 32)};
+            }
         }
         return;
     }
@@ -546,13 +560,14 @@ __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 
 // ---------------------------------------------------------------- fused tile kernel
 //
-// LDS layout (128 KiB, one workgroup per CU):
+// LDS layout (144 KiB, one workgroup per CU):
 //   [0, 64 KiB)        byte-position GHASH table of H^64 for the current key,
 //                      entry-major: the product for byte value v at position
 //                      k sits at byte 256*v + 16*k, so position k lives in
 //                      bank group k (16 groups of four banks).
 //   [64 KiB, 128 KiB)  AES T-tables: entry e of table t, copy c (c = 0..15)
 //                      at 0x10000 + 256*e + 64*t + 4*c.
+//   [128 KiB, 144 KiB) the key's lane fix-up window tables (slot layout).
 //
 // A wave64 ds_read_b32 takes two cycles when no two lanes of a half-wave
 // share a bank; random indices into one 1 KiB table cost about three times
@@ -825,28 +840,37 @@ __device__ __forceinline__ void store_block_partial(uint8_t *p, uint64_t blk, ui
     }
 }
 
-// a * c for a per-lane c in VALU only (a comb over the 32 bit positions of
-// the words of a: 256-bit accumulate with word-aligned XORs, one fold at the
-// end), about 950 VALU instructions and no memory traffic
-__device__ __forceinline__ u32x4 gf_mul_comb(u32x4 a, u32x4 c)
+// LDS byte offset of the lane fix-up window table (after the GHASH table and
+// the T-tables)
+constexpr uint32_t kWinBase = 0x20000u;
+
+// a * c_l for this lane's fixed multiplier c_l = H^(63 - lane), through its
+// 4-bit window table in LDS (entry (v, l) = (v * c_l) mod P at
+// kWinBase + 16 * (64 v + l)): a comb over the eight nibble positions of the
+// four words of a, 256-bit accumulate with word-aligned XORs, one fold at the
+// end.  32 conflict-free ds_read_b128 (16 consecutive lanes read 16
+// different bank groups) and about 300 VALU instructions.
+__device__ __forceinline__ u32x4 gf_mul_lanewin(u32x4 a, const uint8_t *__restrict__ lds, int lane)
 {
-    const uint32_t am[4] = {a.x, a.y, a.z, a.w}, cm[4] = {c.x, c.y, c.z, c.w};
-    const P128 pa = mem_to_poly(am), pc = mem_to_poly(cm);
+    const uint32_t am[4] = {a.x, a.y, a.z, a.w};
+    const P128 pa = mem_to_poly(am);
     const uint32_t aw[4] = {(uint32_t)pa.lo, (uint32_t)(pa.lo >> 32), (uint32_t)pa.hi, (uint32_t)(pa.hi >> 32)};
-    const uint32_t cw[4] = {(uint32_t)pc.lo, (uint32_t)(pc.lo >> 32), (uint32_t)pc.hi, (uint32_t)(pc.hi >> 32)};
+    const uint8_t *win = lds + kWinBase + 16u * (uint32_t)lane;
     uint32_t acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
-    for (int b = 31; b >= 0; --b) {
+    for (int q = 7; q >= 0; --q) {
 #pragma unroll
         for (int k = 7; k > 0; --k)
-            acc[k] = __builtin_amdgcn_alignbit(acc[k], acc[k - 1], 31);  // acc <<= 1
-        acc[0] <<= 1;
+            acc[k] = __builtin_amdgcn_alignbit(acc[k], acc[k - 1], 28);  // acc <<= 4
+        acc[0] <<= 4;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const uint32_t m = 0u - ((aw[w] >> b) & 1u);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                acc[w + j] ^= cw[j] & m;
+            const uint32_t v = (aw[w] >> (4 * q)) & 15u;
+            const u32x4 t = *reinterpret_cast<const u32x4 *>(win + 1024u * v);
+            acc[w] ^= t.x;
+            acc[w + 1] ^= t.y;
+            acc[w + 2] ^= t.z;
+            acc[w + 3] ^= t.w;
         }
     }
     const P128 r = poly_reduce((uint64_t)acc[0] | ((uint64_t)acc[1] << 32), (uint64_t)acc[2] | ((uint64_t)acc[3] << 32),
@@ -1005,10 +1029,8 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     if (!GH)
         return;
 
-    // fix-up: a * H^(63 - lane), multiplied in registers (the powers sit in
-    // one contiguous KiB of the key slot, so this is one coalesced load and no
-    // table gathers at the end of the tile)
-    a = gf_mul_comb(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLanePowOff)[63 - lane]);
+    // fix-up: a * H^(63 - lane) through the lane's window table in LDS
+    a = gf_mul_lanewin(a, lds, lane);
     a = wave_xor_reduce(a);
     if (lane == 0)
         partials[d.tile_base + t] = a;
@@ -1042,6 +1064,33 @@ __device__ __forceinline__ void stage_ttables(u32x4 *lds_v, const uint32_t *__re
     }
 }
 
+// The key's GHASH table of H^64 (64 KiB, LDS bytes [0, 64 KiB)) and its
+// lane fix-up windows (16 KiB, LDS bytes [128 KiB, 144 KiB)) from the key
+// slot, all of a thread's loads issued before its stores.  The caller adds
+// the barriers.
+template <int NT>
+__device__ __forceinline__ void stage_key_tables(u32x4 *lds_v, uint64_t slot)
+{
+    const GLOBAL_AS u32x4 *tab = gptr<const u32x4>(slot + kSlotTab8Off);
+    const GLOBAL_AS u32x4 *win = gptr<const u32x4>(slot + kSlotLaneWinOff);
+    constexpr int kTab = 4096, kWin = 1024;
+    constexpr int kPer = (kTab + kWin + NT - 1) / NT;
+    u32x4 st[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const uint32_t q = threadIdx.x + r * NT;
+        st[r] = q < (uint32_t)kTab ? tab[q] : q < (uint32_t)(kTab + kWin) ? win[q - kTab] : u32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+        const uint32_t q = threadIdx.x + r * NT;
+        if (q < (uint32_t)kTab)
+            lds_v[q] = st[r];
+        else if (q < (uint32_t)(kTab + kWin))
+            lds_v[8192 + (q - kTab)] = st[r];
+    }
+}
+
 // Kernel variants (each a kernel of its own, so that the extra work of one
 // leaves the register allocation of the others alone): GCM; counter mode
 // only; GCM with the GHASH-only pass over whole AAD rows, for single messages
@@ -1060,7 +1109,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
     constexpr bool GH = MODE != kModeCtr;
     constexpr bool AADROWS = MODE == kModeGcmAad;
     constexpr bool J0DEV = MODE == kModeGcmJ0;
-    __shared__ u32x4 lds_v[8192];  // 128 KiB: GHASH table, then the replicated T-tables
+    __shared__ u32x4 lds_v[9216];  // 144 KiB: GHASH table, replicated T-tables, fix-up windows
     const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
 
     if (GH && blockIdx.x == 0 && threadIdx.x == 0)
@@ -1089,20 +1138,7 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
         }
         if (GH && d.slot != cur_slot) {
             lds_barrier();
-            const GLOBAL_AS u32x4 *src = gptr<const u32x4>(d.slot + kSlotTab8Off);
-            constexpr int kPer = (4096 + WAVES * 64 - 1) / (WAVES * 64);
-            u32x4 st[kPer];
-#pragma unroll
-            for (int r = 0; r < kPer; ++r) {
-                const uint32_t q = threadIdx.x + r * WAVES * 64;
-                st[r] = q < 4096u ? src[q] : u32x4{0, 0, 0, 0};
-            }
-#pragma unroll
-            for (int r = 0; r < kPer; ++r) {
-                const uint32_t q = threadIdx.x + r * WAVES * 64;
-                if (q < 4096u)
-                    lds_v[q] = st[r];
-            }
+            stage_key_tables<WAVES * 64>(lds_v, d.slot);
             cur_slot = d.slot;
             lds_barrier();
         }
@@ -1577,7 +1613,7 @@ __device__ void wave_tile_siv(const MsgDesc &d, uint64_t t, const uint8_t *__res
     }
     if (!GH)
         return;
-    a = gf_mul_comb(a, reinterpret_cast<const u32x4 *>(d.slot + kSlotLanePowOff)[63 - lane]);
+    a = gf_mul_lanewin(a, lds, lane);
     a = wave_xor_reduce(a);
     if (lane == 0)
         partials[d.tile_base + t] = a;
@@ -1592,26 +1628,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_siv_tiles(MsgDesc d, uint32_t n_
                                                           u32x4 *__restrict__ partials)
 {
     constexpr bool GH = PASS != kSivCtr, AES = PASS != kSivHash;
-    __shared__ u32x4 lds_v[8192];
+    __shared__ u32x4 lds_v[9216];
     const uint8_t *lds = reinterpret_cast<const uint8_t *>(lds_v);
     if (AES)
         stage_ttables<WAVES * 64>(lds_v, te0g);
-    if (GH) {
-        const GLOBAL_AS u32x4 *src = gptr<const u32x4>(d.slot + kSlotTab8Off);
-        constexpr int kPer = (4096 + WAVES * 64 - 1) / (WAVES * 64);
-        u32x4 st[kPer];
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const uint32_t q = threadIdx.x + r * WAVES * 64;
-            st[r] = q < 4096u ? src[q] : u32x4{0, 0, 0, 0};
-        }
-#pragma unroll
-        for (int r = 0; r < kPer; ++r) {
-            const uint32_t q = threadIdx.x + r * WAVES * 64;
-            if (q < 4096u)
-                lds_v[q] = st[r];
-        }
-    }
+    if (GH)
+        stage_key_tables<WAVES * 64>(lds_v, d.slot);
     lds_barrier();
     const LaneK lk = lane_constants(threadIdx.x & 63);
     const GhK gk = gh_constants(threadIdx.x & 63);
