@@ -221,3 +221,42 @@ def test_siv_full_size_sampled(ctx):
     finally:
         torch.cuda.synchronize()
         ctx.key_release(slot)
+
+
+def test_siv_two_streams_and_odd_tag_offset(ctx):
+    """Two messages in flight on two HIP streams at once, each with its own
+    workspace (nothing else is shared but read-only key data), and tags at
+    odd device offsets (the tag may sit anywhere)."""
+    r = np.random.default_rng(9500)
+    kgk, n1, n2 = r.bytes(32), r.bytes(12), r.bytes(12)
+    p1 = r.integers(0, 256, (2 << 20) + 7, dtype=np.uint8)
+    p2 = r.integers(0, 256, (3 << 20) + 1, dtype=np.uint8)
+    a1 = r.integers(0, 256, 100, dtype=np.uint8)
+    c1, t1 = oracle.gcm_siv_encrypt(kgk, n1, a1, p1)
+    c2, t2 = oracle.gcm_siv_encrypt(kgk, n2, b"", p2)
+    slot = ctx.key_register(kgk)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        pt1, pt2, aad1 = to_dev(p1), to_dev(p2), to_dev(a1)
+        ct1, ct2 = torch.empty_like(pt1), torch.empty_like(pt2)
+        tags = torch.zeros(64, dtype=torch.uint8, device="cuda")
+        ws1 = torch.empty(ctx.siv_workspace_size(p1.size, a1.size), dtype=torch.uint8, device="cuda")
+        ws2 = torch.empty(ctx.siv_workspace_size(p2.size, 0), dtype=torch.uint8, device="cuda")
+        torch.cuda.current_stream().synchronize()
+        ctx.siv_encrypt_async(slot, n1, aad1, pt1, ct1, tags[3:19], workspace=ws1, stream=s1)
+        ctx.siv_encrypt_async(slot, n2, None, pt2, ct2, tags[37:53], workspace=ws2, stream=s2)
+        s1.synchronize()
+        s2.synchronize()
+        assert np.array_equal(host(ct1), c1) and bytes(host(tags[3:19])) == t1
+        assert np.array_equal(host(ct2), c2) and bytes(host(tags[37:53])) == t2
+        ok = torch.full((2,), -1, dtype=torch.int32, device="cuda")
+        b1, b2 = torch.empty_like(pt1), torch.empty_like(pt2)
+        ctx.siv_decrypt_verify_async(slot, n1, aad1, ct1, tags[3:19], b1, ok[0:1], workspace=ws1, stream=s1)
+        ctx.siv_decrypt_verify_async(slot, n2, None, ct2, tags[37:53], b2, ok[1:2], workspace=ws2, stream=s2)
+        s1.synchronize()
+        s2.synchronize()
+        assert host(ok).tolist() == [1, 1]
+        assert np.array_equal(host(b1), p1) and np.array_equal(host(b2), p2)
+    finally:
+        torch.cuda.synchronize()
+        ctx.key_release(slot)
