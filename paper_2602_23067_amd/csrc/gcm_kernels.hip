@@ -553,6 +553,36 @@ __device__ __forceinline__ u32x4 mul_tab4(u32x4 a, const u32x4 *__restrict__ tab
     return r0 ^ r1;
 }
 
+// XOR over the 32 lanes of each half-wave (rows 0-1 and rows 2-3); every lane
+// of the half-wave returns the sum.  All 64 lanes must execute it.
+__device__ __forceinline__ uint32_t half_wave_xor_u32(uint32_t x)
+{
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    x ^= __builtin_amdgcn_update_dpp(0u, x, 0x140, 0xF, 0xF, false);  // row_mirror
+    const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);  // rows 0<->1, 2<->3
+    return p[0] ^ p[1];
+}
+
+// v * M for a v that all 32 lanes of a half-wave hold, with M's
+// nibble-position table: lane q (0..31) reads the entry of nibble position q
+// (one lookup instead of 32), then an XOR across the half-wave.  Every lane of
+// the half-wave returns the product; all 64 lanes of the wave must execute
+// it (active == false: the lane's half-wave contributes zero).
+__device__ __forceinline__ u32x4 mul_tab4_half(u32x4 v, const u32x4 *__restrict__ tab, uint32_t q, bool active)
+{
+    u32x4 t = {0, 0, 0, 0};
+    if (active) {
+        const uint32_t k = q >> 1;  // byte position; even q: its high nibble
+        const uint32_t wsel = k >> 2;
+        const uint32_t word = wsel == 0 ? v.x : wsel == 1 ? v.y : wsel == 2 ? v.z : v.w;
+        const uint32_t byte = (word >> (8 * (k & 3))) & 0xffu;
+        t = tab[q * 16 + ((q & 1) ? (byte & 15u) : (byte >> 4))];
+    }
+    return u32x4{half_wave_xor_u32(t.x), half_wave_xor_u32(t.y), half_wave_xor_u32(t.z), half_wave_xor_u32(t.w)};
+}
+
 __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 {
     return u32x4{wave_xor_u32(a.x), wave_xor_u32(a.y), wave_xor_u32(a.z), wave_xor_u32(a.w)};
@@ -1244,14 +1274,28 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
     lds_barrier();
     for (int lev = 0; lev < nbits; ++lev) {
         const uint32_t pairs = N >> (lev + 1);
-        if (i < pairs) {
-            const uint32_t a = (2 * i) << lev, b = a + (1u << lev);
-            leaf[a] = mul_tab4(leaf[a], tabs[1 + lev]) ^ leaf[b];
+        if (pairs > kCombineThreads / 32) {
+            // wide levels: one thread per pair (bound by LDS bandwidth)
+            if (i < pairs) {
+                const uint32_t a = (2 * i) << lev, b = a + (1u << lev);
+                leaf[a] = mul_tab4(leaf[a], tabs[1 + lev]) ^ leaf[b];
+            }
+        } else {
+            // narrow levels (bound by latency): 32 lanes per pair, one lookup
+            // each; pair i / 32 is uniform across each half-wave, whose reads of
+            // leaf[a] precede its write, and other pairs touch other leaves
+            const uint32_t pp = i >> 5;
+            const bool act = pp < pairs;
+            const uint32_t a = act ? (2 * pp) << lev : 0u, b = act ? a + (1u << lev) : 0u;
+            const u32x4 prod = mul_tab4_half(act ? leaf[a] : u32x4{0, 0, 0, 0}, tabs[1 + lev], i & 31u, act);
+            if (act && (i & 31u) == 0)
+                leaf[a] = prod ^ leaf[b];
         }
         lds_barrier();
     }
+    // * H, by the first half-wave
+    const u32x4 s = mul_tab4_half(i < 32 ? leaf[0] : u32x4{0, 0, 0, 0}, tabs[0], i & 31u, i < 32);
     if (i == 0) {
-        const u32x4 s = mul_tab4(leaf[0], tabs[0]);  // * H
         if (d.yout) {  // a streamed segment: hand on its GHASH value
             *reinterpret_cast<u32x4 *>(d.yout) = s;
             return;
