@@ -34,7 +34,8 @@
  *  - Limits (SP 800-38D): len <= 2^36 - 32 bytes, aad_len < 2^61 bytes,
  *    else GCM_E_TOOLONG.
  *  - in == out is allowed (in place); partially overlapping in/out is
- *    GCM_E_ALIAS.
+ *    GCM_E_ALIAS, and so is an output that overlaps the AAD, the tag or the
+ *    accept flag (these are read or written while the output is written).
  *  - The caller owns every buffer.  The context owns its key table and its
  *    internal scratch.  No call keeps a caller pointer after it returns.
  *  - No C++ exception crosses this interface: a failed host allocation inside
@@ -59,7 +60,7 @@ extern "C" {
 #define GCM_E_NOMEM (-5)   /* device or pinned allocation failed / budget exceeded */
 #define GCM_E_HIP (-6)     /* a HIP runtime call failed */
 #define GCM_E_BUSY (-7)    /* no free key slot / serving queue full */
-#define GCM_E_ALIAS (-8)   /* in and out overlap without being equal */
+#define GCM_E_ALIAS (-8)   /* in and out overlap without being equal, or out overlaps AAD / tag / flag */
 #define GCM_E_SLOT (-9)    /* key slot index not registered */
 #define GCM_E_INTERNAL (-10) /* a host runtime failure other than memory (e.g. a thread that cannot start) */
 
@@ -400,7 +401,9 @@ typedef struct gcm_request {
 typedef struct gcm_serve_config {
     uint32_t n_streams;       /* batches in flight at once (0 = 4, at most 16) */
     uint32_t max_batch_reqs;  /* requests per batch (0 = 256) */
-    uint64_t hbm_budget;      /* device bytes (in + out + AAD) of admitted requests (0 = 64 GiB) */
+    uint64_t hbm_budget;      /* device bytes of admitted requests (in + out + AAD + their share of a
+                                 batch's descriptors and tile partials) plus the loop's retained
+                                 stream-slot memory (0 = 64 GiB) */
     uint64_t max_batch_bytes; /* payload bytes per batch; a larger request runs alone (0 = 256 MiB) */
     uint32_t max_queue;       /* waiting + admitted requests before submit says GCM_E_BUSY (0 = 65536) */
     uint32_t reserved;
@@ -408,10 +411,13 @@ typedef struct gcm_serve_config {
 
 typedef struct gcm_serve_stats {
     uint64_t submitted, completed, rejected, batches;
-    uint64_t bytes_completed;
-    uint64_t budget_high_water;      /* most bytes ever admitted at once (<= hbm_budget) */
+    uint64_t bytes_completed;        /* payload bytes of requests completed without failure */
+    uint64_t budget_high_water;      /* most device bytes ever held at once, as hbm_budget counts them
+                                        (<= hbm_budget) */
     uint64_t overlapped_admissions;  /* requests admitted while another batch was on the GPU */
     uint64_t max_inflight_batches;
+    uint64_t failed;                 /* requests completed with a failure status (their batch could not
+                                        be launched or reported a device error); counted in completed */
     double p50_ms, p99_ms, mean_ms, max_ms;  /* latency: submit -> result known on the host */
     double wall_s;                           /* first submit -> last completion */
 } gcm_serve_stats;
@@ -427,12 +433,16 @@ typedef struct gcm_serve gcm_serve;
 int gcm_serve_start(gcm_ctx *ctx, const gcm_serve_config *cfg, gcm_serve **out);
 
 /* Queue a request (thread-safe, non-blocking).  GCM_E_NOMEM if it alone needs
- * more than the budget, GCM_E_BUSY if the queue is full.  The caller keeps
- * the buffers untouched until the request is reported done. */
+ * more than the budget, GCM_E_BUSY if the queue is full, GCM_E_ALIAS if the
+ * output overlaps the input (other than in place), the AAD or the tag.  The
+ * caller keeps the buffers untouched until the request is reported done. */
 int gcm_serve_submit(gcm_serve *s, const gcm_request *req, uint64_t *id_out);
 
 /* Non-blocking status.  When *done is 1 the request is collected: *accept is
- * the decrypt verdict (1 for encrypt) and *latency_ns its latency. */
+ * the decrypt verdict (1 for encrypt) and *latency_ns its latency.  A request
+ * whose batch failed (launch or device error) is collected with *accept 0 and
+ * the call returns that failure's status (its outputs are undefined: a
+ * decrypt's plaintext may not have been zero-filled, so it must not be used). */
 int gcm_serve_poll(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *latency_ns);
 
 /* Block until the request is done, then collect it as gcm_serve_poll does. */
@@ -456,25 +466,48 @@ int gcm_serve_stop(gcm_serve *s);
  * workgroups per compute unit (0 = automatic). */
 int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_group, uint32_t groups_per_cu);
 
-/* Result of one autotune point. */
+/* Fan-in of the reduction tree over tile partials (the paper's combine of
+ * partial GHASH values): 2, 4, 8 or 16 children per node; 0 = automatic
+ * (the autotune cache, else 2).  Results never depend on it. */
+int gcm_set_combine(gcm_ctx *ctx, uint32_t fanin);
+
+/* Result of an autotune search. */
 typedef struct gcm_tune_result {
-    uint32_t log2_tile_blocks; /* chosen blocks per wave tile (log2) */
+    uint32_t log2_tile_blocks; /* chosen blocks per wave tile (log2); for a batch, the cap on its tiles */
     uint32_t waves_per_group;  /* chosen workgroup size in waves */
     uint32_t candidates;       /* shapes timed */
-    float best_ms;             /* mean time of the chosen shape (one encrypt pass) */
+    float best_ms;             /* mean time of the chosen shape (one encrypt pass / one batch pass) */
     double gbs;                /* payload GB/s of the chosen shape */
+    uint32_t groups_per_cu;    /* chosen resident workgroups per compute unit */
+    uint32_t combine_fanin;    /* chosen fan-in of the reduction tree */
 } gcm_tune_result;
 
 /* Exhaustive launch-shape search for messages of about `len` bytes under
  * `key_len`-byte keys (the paper's per-GPU parameter sweep): every candidate
- * tile size (blocks per lane) and workgroup size is timed `reps` times with
- * HIP events on a scratch message, all candidates must produce the identical
- * tag, and the fastest shape is cached for that (key size, size bucket) and
- * used by every later call without an explicit gcm_set_launch.  Allocates
- * scratch for the duration of the call; blocks until done. */
+ * tile size (blocks per lane), workgroup size, groups per CU (1 up to the
+ * occupancy limit) and reduction fan-in is timed `reps` times with HIP events
+ * on a scratch message, all candidates must produce the identical tag
+ * (GCM_E_INTERNAL otherwise), and the fastest shape is cached for that (key
+ * size, floor(log2 len)) and used by every later single-message call
+ * (one-shot, asynchronous, counter mode, host pipeline, streamed segments;
+ * gcm_workspace_size sizes for it) without an explicit gcm_set_launch.
+ * Allocates scratch for the duration of the call; blocks until done. */
 int gcm_autotune(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32_t reps, gcm_tune_result *out, void *stream);
 
-/* Persist / restore the autotune cache as JSON (restoring rejects a cache
+/* The same search for a batch, run on the caller's jobs (gcm_batch_create's
+ * arguments): workgroup size x groups per CU x cap on the messages' tile
+ * sizes (2^8..2^12 blocks) x fan-in, each point a full pass over the batch
+ * timed `reps` times, every point's tags and accept flags required equal to
+ * the first point's (GCM_E_INTERNAL otherwise).  The winner is cached for
+ * (floor(log2 n), floor(log2 payload bytes)) and used by later
+ * gcm_batch_create calls and serving batches of that shape.  Every pass
+ * rewrites the jobs' outputs, tags and flags, so jobs may not run in place
+ * (GCM_E_ARG) and one job's output may not overlap another's input.
+ * Blocks until done. */
+int gcm_batch_autotune(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes,
+                       uint32_t reps, gcm_tune_result *out, void *stream);
+
+/* Persist / restore both autotune caches as JSON (restoring rejects a cache
  * written on another GPU architecture). */
 int gcm_autotune_save(gcm_ctx *ctx, const char *path);
 int gcm_autotune_load(gcm_ctx *ctx, const char *path);

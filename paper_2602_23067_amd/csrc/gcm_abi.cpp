@@ -52,6 +52,8 @@ int gcm::abi_exception() noexcept
     }
 }
 
+int gcm::plan_error(const PlanError &e) { return fail(e.code, "%s", e.msg); }
+
 extern "C" const char *gcm_last_error(void) { return g_last_error; }
 
 // placeholder IV for fill_desc when set_iv fills the descriptor's IV afterwards
@@ -188,6 +190,19 @@ extern "C" int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t 
     GCM_ABI_CATCH
 }
 
+extern "C" int gcm_set_combine(gcm_ctx *ctx, uint32_t fanin)
+{
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "gcm_set_combine: NULL context");
+        if (fanin && !valid_fanin(fanin))
+            return fail(GCM_E_ARG, "gcm_set_combine: fan-in must be 0, 2, 4, 8 or 16");
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->cfg_fanin = fanin;
+        return GCM_OK;
+    GCM_ABI_CATCH
+}
+
 // ---------------------------------------------------------------- keys
 
 int gcm::register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_t *key_lens, uint32_t n,
@@ -300,93 +315,61 @@ int gcm::cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, ui
 
 // ---------------------------------------------------------------- planning
 
-void gcm::launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc)
+SlotView gcm::slot_view(const gcm_ctx *ctx)
 {
-    const uint32_t w = ctx->cfg_waves ? ctx->cfg_waves : 16;
-    uint32_t g = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)w);
-    *waves = w;
-    *gpc = g;
-    if (ctx->cfg_log2B) {
-        *log2B = ctx->cfg_log2B;
-        return;
-    }
-    // Tile size by makespan: resident wave k runs tiles k, k + R, ... (R
-    // resident waves); tile 0 holds the zero prefix, whose whole rows are
-    // skipped; each tile adds a fixed cost (fix-up, partial) of about
-    // kTileCost blocks.  Ties go to the larger tile (fewer partials).
-    const uint64_t R = (uint64_t)ctx->cu_count * g * w;
-    constexpr uint64_t kTileCost = 64;
-    uint64_t best_cost = ~0ull;
-    uint32_t best_l = 16;
-    for (uint32_t l = 16; l >= 6; --l) {
-        const uint64_t B = 1ull << l;
-        const uint64_t T = (m + B - 1) / B;
-        // tiles of one or two rows only while every tile gets a wave of its
-        // own: short messages then finish in one row's latency, and long ones
-        // never pay for a partial (and a combine step) per row
-        if (l < 8 && T > R)
-            continue;
-        const uint64_t z = T * B - m;
-        const uint64_t n0 = (T + R - 1) / R, n1 = T > 1 ? (T - 1 + R - 1) / R : 0;
-        const uint64_t c0 = (n0 - 1) * B + (B - z / 64 * 64) + kTileCost * n0;
-        const uint64_t c1 = n1 * (B + kTileCost);
-        const uint64_t cost = std::max(c0, c1);
-        if (cost < best_cost) {
-            best_cost = cost;
-            best_l = l;
+    SlotView v;
+    v.base = (uint64_t)ctx->d_slots;
+    v.n_slots = ctx->n_slots;
+    v.used = ctx->slot_used.data();
+    v.nr = ctx->slot_nr.data();
+    return v;
+}
+
+Shape gcm::message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len)
+{
+    Shape sh;
+    TuneEntry t;
+    bool tuned = false;
+    if (!ctx->cfg_log2B && !ctx->cfg_waves) {
+        auto it = ctx->tuned.find((uint64_t)key_bytes << 32 | size_bucket(len));
+        if (it != ctx->tuned.end()) {
+            t = it->second;
+            tuned = true;
         }
     }
-    *log2B = best_l;
+    sh.waves = ctx->cfg_waves ? ctx->cfg_waves : tuned ? t.waves : 16;
+    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (tuned && t.gpc) ? t.gpc : (uint32_t)max_groups_per_cu((int)sh.waves);
+    sh.log2B = ctx->cfg_log2B ? ctx->cfg_log2B
+               : tuned        ? t.log2B
+                              : heuristic_log2B(ghash_blocks(aad_len, len), (uint64_t)ctx->cu_count * sh.gpc * sh.waves);
+    sh.fanin = ctx->cfg_fanin ? ctx->cfg_fanin : (tuned && t.fanin) ? t.fanin : 2;
+    return sh;
 }
 
-void gcm::message_shape(const gcm_ctx *ctx, uint32_t nr, uint64_t len, uint64_t aad_len, uint32_t *log2B,
-                        uint32_t *waves, uint32_t *gpc)
+Shape gcm::batch_shape(const gcm_ctx *ctx, uint64_t n, uint64_t payload, uint64_t m)
 {
-    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    launch_shape(ctx, m, log2B, waves, gpc);
-    uint32_t tl, tw;
-    if (!ctx->cfg_log2B && !ctx->cfg_waves && tuned_shape(ctx, (nr - 6) * 4, len, &tl, &tw)) {
-        *log2B = tl;
-        *waves = tw;
-        *gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)tw);
+    Shape sh;
+    TuneEntry t;
+    bool tuned = false;
+    if (!ctx->cfg_log2B && !ctx->cfg_waves) {
+        auto it = ctx->tuned_batch.find((uint64_t)size_bucket(n) << 32 | size_bucket(payload));
+        if (it != ctx->tuned_batch.end()) {
+            t = it->second;
+            tuned = true;
+        }
     }
-}
-
-void gcm::fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in,
-                    uint64_t out, uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr,
-                    uint32_t log2B, uint32_t waves, uint64_t tile_base)
-{
-    std::memset(d, 0, sizeof *d);
-    d->in = in;
-    d->out = out;
-    d->aad = aad;
-    d->tag = tag;
-    d->ok = ok;
-    d->len = len;
-    d->aad_len = aad_len;
-    d->slot = slot_addr;
-    d->n = (len + 15) / 16;
-    d->na = (aad_len + 15) / 16;
-    d->m = d->na + d->n + 1;
-    const uint64_t B = 1ull << log2B;
-    d->n_tiles = (d->m + B - 1) / B;
-    d->z = d->n_tiles * B - d->m;
-    d->tile_lo = 0;
-    d->tile_hi = d->n_tiles;
-    d->tile_base = tile_base;
-    for (int i = 0; i < 3; ++i)
-        d->iv[i] = (uint32_t)iv[4 * i] | ((uint32_t)iv[4 * i + 1] << 8) | ((uint32_t)iv[4 * i + 2] << 16) |
-                   ((uint32_t)iv[4 * i + 3] << 24);
-    d->op = op;
-    d->log2B = log2B;
-    d->nr = nr;
-    d->groups = (uint32_t)((d->n_tiles + waves - 1) / waves);
-    d->pad0 = 0;
-    d->j0 = 0;
-    d->tag_len = 16;
-    d->ctr_off = 0;
-    d->ystate = 0;
-    d->yout = 0;
+    sh.waves = ctx->cfg_waves ? ctx->cfg_waves : tuned ? t.waves : 16;
+    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (tuned && t.gpc) ? t.gpc : (uint32_t)max_groups_per_cu((int)sh.waves);
+    if (ctx->cfg_log2B)
+        sh.log2B = ctx->cfg_log2B;
+    else if (tuned)
+        sh.log2B = t.log2B;
+    else  // the single-launch tile size of the whole batch's blocks, within 2^8..2^12
+        sh.log2B = std::min<uint32_t>(
+            12, std::max<uint32_t>(8, heuristic_log2B(std::max<uint64_t>(1, m),
+                                                      (uint64_t)ctx->cu_count * sh.gpc * sh.waves)));
+    sh.fanin = ctx->cfg_fanin ? ctx->cfg_fanin : (tuned && t.fanin) ? t.fanin : 2;
+    return sh;
 }
 
 bool gcm::valid_iv_len(size_t n) { return n >= 1 && n <= (size_t)kMaxIvBytes; }
@@ -416,38 +399,21 @@ int gcm::set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStrea
     return GCM_OK;
 }
 
-int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
+int gcm::check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d,
+                       const void *tag_d, uint64_t tag_len, const void *ok_d)
 {
-    if (len > kMaxLen || aad_len > kMaxAad)
-        return fail(GCM_E_TOOLONG, "len %llu / aad_len %llu beyond the SP 800-38D limits",
-                    (unsigned long long)len, (unsigned long long)aad_len);
-    return check_buffers(aad_len, len, aad_d, in_d, out_d);
-}
-
-int gcm::check_buffers(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d)
-{
-    if ((len && (!in_d || !out_d)) || (aad_len && !aad_d))
-        return fail(GCM_E_ARG, "NULL device buffer with non-zero length");
-    const uintptr_t a = (uintptr_t)aad_d, i = (uintptr_t)in_d, o = (uintptr_t)out_d;
-    if ((aad_len && (a & 15)) || (len && ((i & 15) || (o & 15))))
-        return fail(GCM_E_ARG, "device buffers must be 16-byte aligned");
-    if (len && i != o && i < o + len && o < i + len)
-        return fail(GCM_E_ALIAS, "input and output overlap without being identical");
+    PlanError err;
+    if (check_lengths(aad_len, len, &err) ||
+        check_buffers((uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d, tag_len,
+                      (uint64_t)ok_d, &err))
+        return plan_error(err);
     return GCM_OK;
 }
 
-uint64_t gcm::workspace_counter_bytes(uint64_t n_msgs) { return ((4 + 4 * n_msgs) + 255) / 256 * 256; }
-
-// counters, then per message its tile partials followed by two 16-byte slots:
-// E_K(J0), and J0 when the IV is not 96 bits
-uint64_t gcm::workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs)
-{
-    return workspace_counter_bytes(n_msgs) + 16 * (total_tiles + 2 * n_msgs);
-}
-
 // Enqueue the tile kernel for tiles [d.tile_lo, d.tile_hi) of one message on `s`.
-int gcm::launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
+int gcm::launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, const Shape &sh, void *ws, hipStream_t s)
 {
+    const uint32_t waves = sh.waves, gpc = sh.gpc;
     uint32_t *counters = ws ? reinterpret_cast<uint32_t *>(ws) : nullptr;
     uint8_t *partials = ws ? reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1) : nullptr;
     const uint64_t tiles = d.tile_hi - d.tile_lo;
@@ -467,14 +433,14 @@ int gcm::launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint3
 
 // Enqueue the kernels for one message on `s`: tiles, then (GCM only) the
 // combine and, for decrypt-verify, the zero-fill of a rejected output.
-int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s)
+int gcm::launch_single(gcm_ctx *ctx, const MsgDesc &d, const Shape &sh, void *ws, hipStream_t s)
 {
-    int rc = launch_tile_range(ctx, d, waves, gpc, ws, s);
+    int rc = launch_tile_range(ctx, d, sh, ws, s);
     if (rc || d.op == 2)
         return rc;
     uint32_t *counters = reinterpret_cast<uint32_t *>(ws);
     uint8_t *partials = reinterpret_cast<uint8_t *>(ws) + workspace_counter_bytes(1);
-    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, s);
+    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, sh.fanin, s);
     if (e == hipSuccess && d.op == 1) {
         const uint64_t chunks = (d.len / 16 + 255) / 256;
         const uint32_t zgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(chunks, 4096));
@@ -493,13 +459,10 @@ extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_
         if (!ctx)
             return 0;
         std::lock_guard<std::mutex> g(ctx->mu);
-        const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
+        const uint64_t m = ghash_blocks(aad_len, len);
         uint32_t best = 64;
-        for (uint32_t nr : {10u, 12u, 14u}) {  // any key size the call may use
-            uint32_t log2B, waves, gpc;
-            message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
-            best = std::min(best, log2B);
-        }
+        for (uint32_t kb : {16u, 24u, 32u})  // any key size the call may use: the smallest tiles
+            best = std::min(best, message_shape(ctx, kb, len, aad_len).log2B);
         const uint64_t T = (m + (1ull << best) - 1) >> best;
         return workspace_bytes_for(T, 1);
     GCM_ABI_CATCH_VALUE(0)
@@ -530,7 +493,7 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
         return fail(GCM_E_ARG, "NULL argument");
     if (!valid_iv_len(iv_len))
         return fail(GCM_E_IVLEN, "IV length %zu is not in 1..%d", iv_len, kMaxIvBytes);
-    int rc = check_message(aad_len, len, aad_d, in_d, out_d);
+    int rc = check_message(aad_len, len, aad_d, in_d, out_d, tag_d, 16, ok_d);
     if (rc)
         return rc;
     if ((uintptr_t)ws & 15)
@@ -538,13 +501,10 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     std::lock_guard<std::mutex> g(ctx->mu);
     if (slot >= ctx->n_slots || !ctx->slot_used[slot])
         return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
-    uint32_t log2B, waves, gpc;
-    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    launch_shape(ctx, m, &log2B, &waves, &gpc);
+    const Shape sh = message_shape(ctx, (ctx->slot_nr[slot] - 6) * 4, len, aad_len);
     MsgDesc d;
     fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
-              (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), 0, log2B, waves, 0);
-    d.nr = ctx->slot_nr[slot];
+              (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), ctx->slot_nr[slot], sh.log2B, sh.waves, 0);
     if (ws_bytes < workspace_bytes_for(d.n_tiles, 1))
         return fail(GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
                     (unsigned long long)ws_bytes, (unsigned long long)workspace_bytes_for(d.n_tiles, 1));
@@ -555,7 +515,7 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     rc = set_iv(&d, iv, iv_len, ws, s);
     if (rc)
         return rc;
-    return launch_single(ctx, d, waves, gpc, ws, s);
+    return launch_single(ctx, d, sh, ws, s);
 }
 
 extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
@@ -603,10 +563,9 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return fail_hip(e, "hipSetDevice");
-    uint32_t log2B, waves, gpc;
-    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    message_shape(ctx, slot_nr(key_len), len, aad_len, &log2B, &waves, &gpc);
-    const uint64_t T = (m + (1ull << log2B) - 1) >> log2B;
+    const Shape sh = message_shape(ctx, (uint32_t)key_len, len, aad_len);
+    const uint64_t m = ghash_blocks(aad_len, len);
+    const uint64_t T = (m + (1ull << sh.log2B) - 1) >> sh.log2B;
     rc = ensure_ws_locked(ctx, workspace_bytes_for(T, 1));
     if (rc)
         return rc;
@@ -623,12 +582,12 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     }
     MsgDesc d;
     fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)d_tag,
-              (uint64_t)d_ok, (uint64_t)(ctx->d_slots + kSlotBytes * slot), slot_nr(key_len), log2B, waves, 0);
+              (uint64_t)d_ok, (uint64_t)(ctx->d_slots + kSlotBytes * slot), slot_nr(key_len), sh.log2B, sh.waves, 0);
     d.tag_len = (uint32_t)tag_len;
     rc = set_iv(&d, iv, iv_len, ctx->d_ws, s);
     if (rc)
         return rc;
-    rc = launch_single(ctx, d, waves, gpc, ctx->d_ws, s);
+    rc = launch_single(ctx, d, sh, ctx->d_ws, s);
     if (rc)
         return rc;
     e = hipMemcpyAsync(ctx->h_io, ctx->d_io, 32, hipMemcpyDeviceToHost, s);
@@ -691,12 +650,11 @@ extern "C" int gcm_decrypt_verify(gcm_ctx *ctx, const uint8_t *key, size_t key_l
 static int ctr_common(gcm_ctx *ctx, uint32_t slot, uint32_t nr, const uint8_t *iv, const uint8_t *in_d, uint64_t len,
                       uint8_t *out_d, hipStream_t s)
 {
-    uint32_t log2B, waves, gpc;
-    message_shape(ctx, nr, len, 0, &log2B, &waves, &gpc);
+    const Shape sh = message_shape(ctx, (nr - 6) * 4, len, 0);
     MsgDesc d;
     fill_desc(&d, 2, iv, 0, 0, (uint64_t)in_d, (uint64_t)out_d, len, 0, 0,
-              (uint64_t)(ctx->d_slots + kSlotBytes * slot), nr, log2B, waves, 0);
-    return launch_single(ctx, d, waves, gpc, nullptr, s);
+              (uint64_t)(ctx->d_slots + kSlotBytes * slot), nr, sh.log2B, sh.waves, 0);
+    return launch_single(ctx, d, sh, nullptr, s);
 }
 
 static int check_ctr_args(const void *iv, size_t iv_len, const uint8_t *in_d, uint64_t len, const uint8_t *out_d)

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gcm_internal.h"
+#include "gcm_plan.h"
 
 struct gcm_ctx {
     int device = 0;
@@ -31,9 +32,11 @@ struct gcm_ctx {
     uint8_t *d_io = nullptr;  // device tag (16 B) + flag (4 B)
     uint8_t *h_io = nullptr;  // pinned mirror
     // launch shape overrides (0 = automatic)
-    uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0;
-    // autotune cache: (key bytes << 32 | floor(log2 len)) -> (log2 tile blocks, waves)
-    std::unordered_map<uint64_t, std::pair<uint32_t, uint32_t>> tuned;
+    uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0, cfg_fanin = 0;
+    // autotune caches: single messages keyed by (key bytes << 32 | floor(log2
+    // len)); batches keyed by (floor(log2 messages) << 32 | floor(log2 payload))
+    std::unordered_map<uint64_t, gcm::TuneEntry> tuned;
+    std::unordered_map<uint64_t, gcm::TuneEntry> tuned_batch;
     // tile-kernel timing (events recorded on the launch stream)
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_pending;
@@ -79,10 +82,9 @@ struct gcm_ctx {
 
 namespace gcm {
 
-constexpr uint64_t kMaxLen = (1ull << 36) - 32;  // 2^39 - 256 bits
-constexpr uint64_t kMaxAad = (1ull << 61) - 1;   // < 2^64 bits
-
 int fail(int code, const char *fmt, ...);
+// record a planning error as the thread's last error and return its code
+int plan_error(const PlanError &e);
 int fail_hip(hipError_t e, const char *what);
 // The status for the exception in flight (called from a catch block):
 // std::bad_alloc -> GCM_E_NOMEM, anything else -> GCM_E_INTERNAL, with the
@@ -95,26 +97,36 @@ int register_key_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32
 int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_t *key_lens, uint32_t n,
                          uint32_t *slots_out, hipStream_t s);
 
-void launch_shape(const gcm_ctx *ctx, uint64_t m, uint32_t *log2B, uint32_t *waves, uint32_t *gpc);
-// shape for one message: explicit settings, else the autotune cache, else the heuristic
-void message_shape(const gcm_ctx *ctx, uint32_t nr, uint64_t len, uint64_t aad_len, uint32_t *log2B, uint32_t *waves,
-                   uint32_t *gpc);
-bool tuned_shape(const gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32_t *log2B, uint32_t *waves);
-void fill_desc(MsgDesc *d, uint32_t op, const uint8_t *iv, uint64_t aad, uint64_t aad_len, uint64_t in, uint64_t out,
-               uint64_t len, uint64_t tag, uint64_t ok, uint64_t slot_addr, uint32_t nr, uint32_t log2B,
-               uint32_t waves, uint64_t tile_base);
-int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
-// NULL, alignment (16 B) and partial-overlap checks of device buffers
-int check_buffers(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d);
-uint64_t workspace_counter_bytes(uint64_t n_msgs);
-uint64_t workspace_bytes_for(uint64_t total_tiles, uint64_t n_msgs);
+// Launch shape of one message: explicit settings (gcm_set_launch), else the
+// autotune cache entry for (key size, message size), else the heuristic.
+// Every single-message path (one-shot, asynchronous, counter mode, host
+// pipeline, streamed segments, GCM-SIV) and gcm_workspace_size use it.
+Shape message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len);
+// Launch shape of a batch of n messages and `payload` bytes holding m GHASH
+// blocks in all: explicit settings, else the batch autotune cache, else the
+// heuristic (tile cap from the single-launch heuristic, 16 waves).
+Shape batch_shape(const gcm_ctx *ctx, uint64_t n, uint64_t payload, uint64_t m);
+// the key table as the planner sees it
+SlotView slot_view(const gcm_ctx *ctx);
+// lengths and device buffers of one message (see check_buffers)
+int check_message(uint64_t aad_len, uint64_t len, const void *aad_d, const void *in_d, const void *out_d,
+                  const void *tag_d = nullptr, uint64_t tag_len = 16, const void *ok_d = nullptr);
 // IV lengths the device path takes (1..kMaxIvBytes bytes)
 bool valid_iv_len(size_t n);
 // Set the descriptor's IV: 12 bytes go in d.iv; any other length enqueues the
 // J0 kernel on `s` (d.slot must be set), writing J0 to the message's J0 slot
 // of workspace `ws` (after its partials and E_K(J0)), and points d.j0 there.
 int set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStream_t s);
-int launch_single(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
+int launch_single(gcm_ctx *ctx, const MsgDesc &d, const Shape &sh, void *ws, hipStream_t s);
+// batches (gcm_batch.cpp; caller holds ctx->mu): validate and plan jobs
+// (with `forced` as the shape if non-NULL), create a batch, enqueue its
+// kernels, free it
+int plan_jobs(const gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes,
+              const Shape *forced, Shape *sh_out, BatchPlan *plan);
+int batch_create_locked(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes,
+                        const Shape *forced, gcm_batch **out);
+hipError_t batch_enqueue(gcm_batch *b, hipStream_t s);
+void batch_free_locked(gcm_batch *b);
 // release the host pipeline's streams, events and buffers (gcm_ctx_destroy)
 void pipeline_release(gcm_ctx *ctx);
 // ensure the context's one-shot workspace holds `bytes` (caller holds ctx->mu)
@@ -122,7 +134,7 @@ int ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes);
 // one-shot key cache lookup / expansion (caller holds ctx->mu)
 int cached_slot_locked(gcm_ctx *ctx, const uint8_t *key, size_t key_len, uint32_t *slot, hipStream_t s);
 // tile kernel only, for tiles [d.tile_lo, d.tile_hi); ws may be NULL for op 2
-int launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *ws, hipStream_t s);
+int launch_tile_range(gcm_ctx *ctx, const MsgDesc &d, const Shape &sh, void *ws, hipStream_t s);
 // bracket the next tile launch with events when profiling is on (caller holds ctx->mu)
 hipError_t prof_begin(gcm_ctx *ctx, hipStream_t s);
 hipError_t prof_end(gcm_ctx *ctx, hipStream_t s);
@@ -136,8 +148,9 @@ hipError_t launch_tiles(int waves, const MsgDesc *descs, const WorkItem *items, 
                         const MsgDesc *single, const uint32_t *te0, void *partials, uint32_t *counters, uint32_t grid,
                         hipStream_t s);
 int max_groups_per_cu(int waves);
+// fanin: children per node of the reduction tree over tile partials (2, 4, 8, 16)
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
-                          uint32_t *counters, hipStream_t s);
+                          uint32_t *counters, uint32_t fanin, hipStream_t s);
 hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);

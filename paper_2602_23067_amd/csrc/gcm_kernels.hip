@@ -1193,13 +1193,16 @@ constexpr int kCombineLog2 = 10;
 // Horner over partials i, i+1024, ... with the fixed multiplier H^(1024*B);
 // its value then needs the weight H^((T-1-t_last)*B), and with N = 2^k >=
 // min(T, 1024) leaves and r = T mod N that weight is H^((N-1-j)*B) for leaf
-// j = (i - r) mod N.  A binary tree over the leaves, L*H^(B*2^lev) ^ R at
-// level lev, closes the sum in k levels with N - 1 products in all; one more
-// *H accounts for GHASH's final multiplication.  The nibble tables this needs
+// j = (i - r) mod N.  A tree of fan-in F = 2^LOGF over the leaves closes the
+// sum: a node whose F children each span w leaves is the Horner
+// (((c_0*H^(B*w) ^ c_1)*H^(B*w) ^ c_2) ...) ^ c_(F-1), so the levels use the
+// tables of H^(B*2^(LOGF*lev)) and the tree has ceil(k / LOGF) levels and
+// N - 1 products in all (F = 2 is the binary tree L*H^(B*2^lev) ^ R); one
+// more *H accounts for GHASH's final multiplication.  The nibble tables this needs
 // (at most 12 of 8 KiB) are staged in LDS first, so every multiply is 32 LDS
 // reads.  E_K(J0) was left by the tile kernel right after the message's T
 // partials.
-template <bool BATCH>
+template <bool BATCH, int LOGF>
 __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *__restrict__ descs, MsgDesc single,
                                                                  const u32x4 *__restrict__ partials,
                                                                  uint32_t *counters)
@@ -1272,24 +1275,36 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
     if (i < N)
         leaf[(i - r) & (N - 1)] = acc;
     lds_barrier();
-    for (int lev = 0; lev < nbits; ++lev) {
-        const uint32_t pairs = N >> (lev + 1);
-        if (pairs > kCombineThreads / 32) {
-            // wide levels: one thread per pair (bound by LDS bandwidth)
-            if (i < pairs) {
-                const uint32_t a = (2 * i) << lev, b = a + (1u << lev);
-                leaf[a] = mul_tab4(leaf[a], tabs[1 + lev]) ^ leaf[b];
+    for (int lev = 0; lev < nbits; lev += LOGF) {
+        const int span = nbits - lev < LOGF ? nbits - lev : LOGF;  // log2 of this level's children per node
+        const uint32_t kids = 1u << span, w = 1u << lev;           // children, leaves per child
+        const uint32_t nodes = N >> (lev + span);
+        const u32x4 *tab = tabs[1 + lev];                            // H^(B*w)
+        if (nodes > kCombineThreads / 32) {
+            // wide levels: one thread per node (bound by LDS bandwidth)
+            if (i < nodes) {
+                const uint32_t a = i << (lev + span);
+                u32x4 v = leaf[a];
+                for (uint32_t c = 1; c < kids; ++c)
+                    v = mul_tab4(v, tab) ^ leaf[a + c * w];
+                leaf[a] = v;
             }
         } else {
-            // narrow levels (bound by latency): 32 lanes per pair, one lookup
-            // each; pair i / 32 is uniform across each half-wave, whose reads of
-            // leaf[a] precede its write, and other pairs touch other leaves
+            // narrow levels (bound by latency): 32 lanes per node, one lookup
+            // each per product; node i / 32 is uniform across each half-wave,
+            // whose reads of its leaves precede its write, and other nodes
+            // touch other leaves
             const uint32_t pp = i >> 5;
-            const bool act = pp < pairs;
-            const uint32_t a = act ? (2 * pp) << lev : 0u, b = act ? a + (1u << lev) : 0u;
-            const u32x4 prod = mul_tab4_half(act ? leaf[a] : u32x4{0, 0, 0, 0}, tabs[1 + lev], i & 31u, act);
+            const bool act = pp < nodes;
+            const uint32_t a = act ? pp << (lev + span) : 0u;
+            u32x4 v = act ? leaf[a] : u32x4{0, 0, 0, 0};
+            for (uint32_t c = 1; c < kids; ++c) {
+                v = mul_tab4_half(v, tab, i & 31u, act);
+                if (act)
+                    v ^= leaf[a + c * w];
+            }
             if (act && (i & 31u) == 0)
-                leaf[a] = prod ^ leaf[b];
+                leaf[a] = v;
         }
         lds_barrier();
     }
@@ -1796,16 +1811,38 @@ int max_groups_per_cu(int waves)
     return (e == hipSuccess && n > 0) ? n : 1;
 }
 
+template <int LOGF>
+static void launch_combine_f(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const u32x4 *p,
+                             uint32_t *counters, hipStream_t s)
+{
+    if (descs)
+        hipLaunchKernelGGL((k_gcm_combine<true, LOGF>), dim3(n_msgs), dim3(kCombineThreads), 0, s, descs, MsgDesc{},
+                           p, counters);
+    else
+        hipLaunchKernelGGL((k_gcm_combine<false, LOGF>), dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, p,
+                           counters);
+}
+
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
-                          uint32_t *counters, hipStream_t s)
+                          uint32_t *counters, uint32_t fanin, hipStream_t s)
 {
     const u32x4 *p = reinterpret_cast<const u32x4 *>(partials);
-    if (descs)
-        hipLaunchKernelGGL(k_gcm_combine<true>, dim3(n_msgs), dim3(kCombineThreads), 0, s, descs, MsgDesc{}, p,
-                           counters);
-    else
-        hipLaunchKernelGGL(k_gcm_combine<false>, dim3(1), dim3(kCombineThreads), 0, s, nullptr, *single, p,
-                           counters);
+    switch (fanin) {
+    case 2:
+        launch_combine_f<1>(descs, n_msgs, single, p, counters, s);
+        break;
+    case 4:
+        launch_combine_f<2>(descs, n_msgs, single, p, counters, s);
+        break;
+    case 8:
+        launch_combine_f<3>(descs, n_msgs, single, p, counters, s);
+        break;
+    case 16:
+        launch_combine_f<4>(descs, n_msgs, single, p, counters, s);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

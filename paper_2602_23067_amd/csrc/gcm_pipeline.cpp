@@ -141,8 +141,8 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
     if (rc)
         return rc;
     const uint32_t nr = (uint32_t)(key_len / 4 + 6);
-    uint32_t log2B, waves, gpc;
-    message_shape(ctx, nr, len, aad_len, &log2B, &waves, &gpc);
+    const Shape shape = message_shape(ctx, (nr - 6) * 4, len, aad_len);
+    const uint32_t log2B = shape.log2B, waves = shape.waves;
     const uint64_t B = 1ull << log2B;
     MsgDesc d;
     static const uint8_t zero_iv[12] = {0};
@@ -207,7 +207,7 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
         dc.tile_lo = t0;
         dc.tile_hi = t1;
         dc.in = dc.out = (uint64_t)buf - blo;
-        rc = launch_tile_range(ctx, dc, waves, gpc, ctx->d_ws, sc);
+        rc = launch_tile_range(ctx, dc, shape, ctx->d_ws, sc);
         if (rc)
             break;
         if (data) {
@@ -226,7 +226,7 @@ static int run_pipeline(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t ke
     if (rc == GCM_OK && e == hipSuccess) {
         uint32_t *counters = reinterpret_cast<uint32_t *>(ctx->d_ws);
         const uint8_t *partials = ctx->d_ws + workspace_counter_bytes(1);
-        e = launch_combine(nullptr, 1, &d, partials, counters, sc);
+        e = launch_combine(nullptr, 1, &d, partials, counters, shape.fanin, sc);
         if (e == hipSuccess)
             e = hipMemcpyAsync(ctx->h_io, ctx->d_io, 32, hipMemcpyDeviceToHost, sc);
     }

@@ -42,6 +42,7 @@ struct ReqState {
     int64_t t_submit = 0, t_done = 0;
     int state = 0;  // 0 queued, 1 running, 2 done
     int accept = 1;
+    int status = GCM_OK;  // a failure of the batch that carried the request
 };
 
 // Device and pinned staging of one stream slot; grown on demand while idle.
@@ -52,6 +53,7 @@ struct Slot {
     std::vector<uint64_t> ids;
     uint8_t *d_mem = nullptr;  // descs | items | flags | workspace
     uint64_t d_bytes = 0;
+    uint64_t in_use = 0;       // bytes of d_mem the running batch uses
     uint8_t *h_mem = nullptr;  // pinned: descs | items | flags
     uint64_t h_bytes = 0;
     uint64_t flag_off = 0;  // offset of the accept flags in both blocks
@@ -73,21 +75,40 @@ struct gcm_serve {
     std::thread worker;
     bool stopping = false;
     int worker_error = GCM_OK;
+    char error_msg[256] = {0};
     // statistics
     std::vector<double> lat_ms;
-    uint64_t submitted = 0, completed = 0, rejected = 0, batches = 0, bytes_done = 0;
+    uint64_t submitted = 0, completed = 0, rejected = 0, failed = 0, batches = 0, bytes_done = 0;
     uint64_t overlapped_admissions = 0, max_inflight = 0;
     int64_t t_first = 0, t_last = 0;
 };
 
+// Stream-slot memory not used by a running batch counts against the HBM
+// budget (caller holds s->mu).
+static void update_slack(gcm_serve *s)
+{
+    uint64_t slack = 0;
+    for (const Slot &sl : s->slots)
+        slack += sl.busy ? sl.d_bytes - sl.in_use : sl.d_bytes;
+    s->policy.set_slack(slack);
+}
+
+// Give slot `sl` at least dbytes of device memory and hbytes of pinned
+// staging.  A slot that must grow takes twice its old size when that still
+// fits the budget (fewer regrowths), else exactly dbytes: its requests'
+// admitted bytes already cover dbytes, so the budget holds either way.
 static int slot_reserve(gcm_serve *s, Slot &sl, uint64_t dbytes, uint64_t hbytes)
 {
-    std::lock_guard<std::mutex> g(s->ctx->mu);  // the context's allocation bookkeeping
     if (sl.d_bytes < dbytes) {
+        const uint64_t others = s->policy.slack() - sl.d_bytes;  // the slot is idle: all of it is slack
+        uint64_t want = dbytes;
+        const uint64_t grown = std::max<uint64_t>(dbytes, 2 * sl.d_bytes);
+        if (grown > dbytes && s->policy.admitted_bytes() + others + (grown - dbytes) <= s->cfg.hbm_budget)
+            want = grown;
+        std::lock_guard<std::mutex> g(s->ctx->mu);  // the context's allocation bookkeeping
         ctx_free(s->ctx, sl.d_mem, sl.d_bytes);
         sl.d_mem = nullptr;
         sl.d_bytes = 0;
-        const uint64_t want = std::max<uint64_t>(dbytes, 1ull << 20);
         int rc = ctx_alloc(s->ctx, reinterpret_cast<void **>(&sl.d_mem), want);
         if (rc)
             return rc;
@@ -107,40 +128,53 @@ static int slot_reserve(gcm_serve *s, Slot &sl, uint64_t dbytes, uint64_t hbytes
     return GCM_OK;
 }
 
+// Free the device memory of idle slots (when the head of the queue does not
+// fit beside it and nothing is running).
+static void release_idle_slots(gcm_serve *s)
+{
+    std::lock_guard<std::mutex> g(s->ctx->mu);
+    for (Slot &sl : s->slots)
+        if (!sl.busy && sl.d_mem) {
+            ctx_free(s->ctx, sl.d_mem, sl.d_bytes);
+            sl.d_mem = nullptr;
+            sl.d_bytes = 0;
+        }
+}
+
 // Launch one batch on a free slot (caller holds s->mu).
 static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &batch)
 {
     gcm_ctx *ctx = s->ctx;
     const uint32_t n = (uint32_t)batch.size();
-    uint32_t log2B_cfg, waves, gpc;
-    uint64_t total_m = 0;
-    for (const PolicyReq &p : batch) {
-        const gcm_request &r = s->reqs[p.id].r;
-        total_m += (r.aad_len + 15) / 16 + (r.len + 15) / 16 + 1;
-    }
-    launch_shape(ctx, std::max<uint64_t>(1, total_m), &log2B_cfg, &waves, &gpc);
-
-    std::vector<MsgDesc> descs(n);
-    uint64_t tile_base = 0, n_tiles = 0, n_items = 0;
-    bool any_dec = false;
+    std::vector<PlanMsg> msgs(n);
+    uint64_t total_m = 0, payload = 0;
     for (uint32_t i = 0; i < n; ++i) {
         const gcm_request &r = s->reqs[batch[i].id].r;
-        const uint64_t m = (r.aad_len + 15) / 16 + (r.len + 15) / 16 + 1;
-        uint32_t l = 6;
-        while ((1ull << l) * waves < m && l < 12)
-            ++l;
-        l = std::min(l, std::max<uint32_t>(8, log2B_cfg));
-        fill_desc(&descs[i], r.op, r.iv, (uint64_t)r.aad_d, r.aad_len, (uint64_t)r.in_d, (uint64_t)r.out_d, r.len,
-                  (uint64_t)r.tag_d, 0, (uint64_t)(ctx->d_slots + kSlotBytes * r.key_slot), ctx->slot_nr[r.key_slot],
-                  l, waves, tile_base);
-        tile_base += descs[i].n_tiles + 2;  // partials, then the E_K(J0) and J0 slots
-        n_tiles += descs[i].n_tiles;
-        n_items += descs[i].groups;
-        any_dec |= r.op == 1;
+        PlanMsg &pm = msgs[i];
+        pm.op = r.op;
+        pm.key_slot = r.key_slot;
+        std::memcpy(pm.iv, r.iv, 12);
+        pm.aad = (uint64_t)r.aad_d;
+        pm.aad_len = r.aad_len;
+        pm.in = (uint64_t)r.in_d;
+        pm.out = (uint64_t)r.out_d;
+        pm.len = r.len;
+        pm.tag = (uint64_t)r.tag_d;
+        total_m += ghash_blocks(r.aad_len, r.len);
+        payload += r.len;
     }
+    BatchPlan plan;
+    Shape sh;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);  // key table and autotune caches
+        sh = batch_shape(ctx, n, payload, total_m);
+        plan_batch(msgs.data(), n, slot_view(ctx), sh.waves, sh.log2B, &plan);
+    }
+    const uint64_t n_items = plan.items.size();
     const uint64_t desc_b = align256(n * sizeof(MsgDesc)), item_b = align256(n_items * sizeof(WorkItem));
-    const uint64_t flag_b = align256(4ull * n), ws_b = workspace_bytes_for(n_tiles, n);
-    int rc = slot_reserve(s, sl, desc_b + item_b + flag_b + ws_b, desc_b + item_b + flag_b);
+    const uint64_t flag_b = align256(4ull * n), ws_b = plan.workspace_bytes();
+    const uint64_t dbytes = desc_b + item_b + flag_b + ws_b;
+    int rc = slot_reserve(s, sl, dbytes, desc_b + item_b + flag_b);
     if (rc)
         return rc;
     MsgDesc *h_desc = reinterpret_cast<MsgDesc *>(sl.h_mem);
@@ -151,60 +185,86 @@ static int launch_batch(gcm_serve *s, Slot &sl, const std::vector<PolicyReq> &ba
     int32_t *h_flags = reinterpret_cast<int32_t *>(sl.h_mem + desc_b + item_b);
     uint8_t *d_ws = sl.d_mem + desc_b + item_b + flag_b;
     sl.flag_off = desc_b + item_b;
-    uint64_t k = 0;
     for (uint32_t i = 0; i < n; ++i) {
-        descs[i].ok = (uint64_t)(d_flags + i);
-        h_desc[i] = descs[i];
-        for (uint64_t t = 0; t < descs[i].n_tiles; t += waves)
-            h_item[k++] = WorkItem{i, (uint32_t)t};
-        h_flags[i] = 1;
+        plan.descs[i].ok = (uint64_t)(d_flags + i);
+        h_desc[i] = plan.descs[i];
+        // a decrypt is accepted only once the device has written 1 here
+        h_flags[i] = 0;
     }
-    const uint32_t grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_items, (uint64_t)ctx->cu_count * gpc));
+    if (n_items)
+        std::memcpy(h_item, plan.items.data(), n_items * sizeof(WorkItem));
+    const uint32_t grid =
+        (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(n_items, (uint64_t)ctx->cu_count * sh.gpc));
     hipError_t e = hipMemcpyAsync(sl.d_mem, sl.h_mem, desc_b + item_b, hipMemcpyHostToDevice, sl.stream);
     uint32_t *counters = reinterpret_cast<uint32_t *>(d_ws);
     uint8_t *partials = d_ws + workspace_counter_bytes(n);
     if (e == hipSuccess)
-        e = launch_tiles((int)waves, d_desc, d_item, (uint32_t)n_items, nullptr, ctx->d_tables, partials, counters, grid,
-                         sl.stream);
+        e = launch_tiles((int)sh.waves, d_desc, d_item, (uint32_t)n_items, nullptr, ctx->d_tables, partials, counters,
+                         grid, sl.stream);
     if (e == hipSuccess)
-        e = launch_combine(d_desc, n, nullptr, partials, counters, sl.stream);
-    if (e == hipSuccess && any_dec)
+        e = launch_combine(d_desc, n, nullptr, partials, counters, sh.fanin, sl.stream);
+    if (e == hipSuccess && plan.any_decrypt)
         e = launch_zerofill(d_desc, nullptr, counters, (uint32_t)std::max(1, ctx->cu_count * 2), sl.stream);
-    if (e == hipSuccess && any_dec)
+    if (e == hipSuccess && plan.any_decrypt)
         e = hipMemcpyAsync(h_flags, d_flags, 4ull * n, hipMemcpyDeviceToHost, sl.stream);
     if (e == hipSuccess)
         e = hipEventRecord(sl.done, sl.stream);
     if (e != hipSuccess)
         return fail_hip(e, "serving batch launch");
     sl.busy = true;
+    sl.in_use = dbytes;
     sl.ids.clear();
     for (const PolicyReq &p : batch) {
         sl.ids.push_back(p.id);
         s->reqs[p.id].state = 1;
     }
     s->batches++;
+    update_slack(s);
     return GCM_OK;
 }
 
-static void retire(gcm_serve *s, Slot &sl)
+// Complete a request (caller holds s->mu): err != GCM_OK marks a request
+// whose batch failed; it is reported with that status and never accepted.
+static void finish(gcm_serve *s, uint64_t id, int64_t t, int accept, int err)
 {
-    const int64_t t = now_ns();
-    const int32_t *h_flags = reinterpret_cast<const int32_t *>(sl.h_mem + sl.flag_off);
-    for (size_t i = 0; i < sl.ids.size(); ++i) {
-        ReqState &st = s->reqs[sl.ids[i]];
-        st.state = 2;
-        st.t_done = t;
-        st.accept = st.r.op == 1 ? (h_flags[i] == 1 ? 1 : 0) : 1;
-        s->policy.complete(st.need);
-        s->lat_ms.push_back((double)(t - st.t_submit) * 1e-6);
-        s->completed++;
+    ReqState &st = s->reqs[id];
+    st.state = 2;
+    st.t_done = t;
+    st.status = err;
+    st.accept = err ? 0 : accept;
+    s->policy.complete(st.need);
+    s->lat_ms.push_back((double)(t - st.t_submit) * 1e-6);
+    s->completed++;
+    if (err)
+        s->failed++;
+    else {
         s->bytes_done += st.r.len;
         if (!st.accept)
             s->rejected++;
     }
+}
+
+static void record_error(gcm_serve *s, int code)
+{
+    s->worker_error = code;
+    std::snprintf(s->error_msg, sizeof s->error_msg, "%s", gcm_last_error());
+}
+
+// A batch's event completed (err == GCM_OK) or reported a failure.
+static void retire(gcm_serve *s, Slot &sl, int err)
+{
+    const int64_t t = now_ns();
+    const int32_t *h_flags = reinterpret_cast<const int32_t *>(sl.h_mem + sl.flag_off);
+    for (size_t i = 0; i < sl.ids.size(); ++i) {
+        const ReqState &st = s->reqs[sl.ids[i]];
+        const int accept = st.r.op == 1 ? (h_flags[i] == 1 ? 1 : 0) : 1;
+        finish(s, sl.ids[i], t, accept, err);
+    }
     s->t_last = t;
     sl.busy = false;
+    sl.in_use = 0;
     sl.ids.clear();
+    update_slack(s);
 }
 
 static void worker_loop(gcm_serve *s, std::unique_lock<std::mutex> &lk)
@@ -218,13 +278,13 @@ static void worker_loop(gcm_serve *s, std::unique_lock<std::mutex> &lk)
                 continue;
             const hipError_t q = hipEventQuery(sl.done);
             if (q == hipSuccess) {
-                retire(s, sl);
+                retire(s, sl, GCM_OK);
                 progressed = true;
             } else if (q == hipErrorNotReady) {
                 any_busy = true;
             } else {
-                s->worker_error = fail_hip(q, "serving batch");
-                retire(s, sl);
+                record_error(s, fail_hip(q, "serving batch"));
+                retire(s, sl, s->worker_error);
                 progressed = true;
             }
         }
@@ -232,6 +292,17 @@ static void worker_loop(gcm_serve *s, std::unique_lock<std::mutex> &lk)
             s->cv_done.notify_all();
         admitted.clear();
         s->policy.admit(&admitted);
+        if (admitted.empty() && s->policy.pending() > 0 && s->policy.ready() == 0) {
+            bool idle = true;
+            for (const Slot &sl : s->slots)
+                idle &= !sl.busy;
+            if (idle && s->policy.slack() > 0) {
+                // the head request does not fit beside the retained slot memory
+                release_idle_slots(s);
+                update_slack(s);
+                s->policy.admit(&admitted);
+            }
+        }
         if (any_busy)
             s->overlapped_admissions += admitted.size();
         uint64_t inflight = 0;
@@ -239,15 +310,12 @@ static void worker_loop(gcm_serve *s, std::unique_lock<std::mutex> &lk)
             if (!sl.busy && s->policy.ready() > 0 && s->policy.next_batch(&batch)) {
                 int rc = launch_batch(s, sl, batch);
                 if (rc) {
-                    // the batch could not be launched: fail its requests as rejected
-                    s->worker_error = rc;
-                    for (const PolicyReq &p : batch) {
-                        ReqState &st = s->reqs[p.id];
-                        st.state = 2;
-                        st.accept = 0;
-                        st.t_done = now_ns();
-                        s->policy.complete(st.need);
-                    }
+                    // the batch could not be launched: its requests fail with that status
+                    record_error(s, rc);
+                    const int64_t t = now_ns();
+                    for (const PolicyReq &p : batch)
+                        finish(s, p.id, t, 0, rc);
+                    s->t_last = t;
                     s->cv_done.notify_all();
                 }
             }
@@ -282,18 +350,20 @@ static void worker_main(gcm_serve *s)
     } catch (...) {
         if (!lk.owns_lock())
             lk.lock();
-        s->worker_error = abi_exception();
-        const int64_t t = now_ns();
+        record_error(s, abi_exception());
         for (Slot &sl : s->slots)
             if (sl.busy) {
                 (void)hipEventSynchronize(sl.done);
                 sl.busy = false;
             }
+        const int64_t t = now_ns();
         for (auto &kv : s->reqs)
             if (kv.second.state != 2) {
                 kv.second.state = 2;
                 kv.second.accept = 0;
+                kv.second.status = s->worker_error;
                 kv.second.t_done = t;
+                s->failed++;
             }
         s->cv_done.notify_all();
     }
@@ -370,7 +440,7 @@ extern "C" int gcm_serve_submit(gcm_serve *s, const gcm_request *req, uint64_t *
             return fail(GCM_E_ARG, "gcm_serve_submit: bad op or reserved field");
         if (!r.tag_d)
             return fail(GCM_E_ARG, "gcm_serve_submit: tag_d is required");
-        int rc = check_message(r.aad_len, r.len, r.aad_d, r.in_d, r.out_d);
+        int rc = check_message(r.aad_len, r.len, r.aad_d, r.in_d, r.out_d, r.tag_d, 16);
         if (rc)
             return rc;
         {
@@ -378,7 +448,7 @@ extern "C" int gcm_serve_submit(gcm_serve *s, const gcm_request *req, uint64_t *
             if (r.key_slot >= s->ctx->n_slots || !s->ctx->slot_used[r.key_slot])
                 return fail(GCM_E_SLOT, "key slot %u is not registered", r.key_slot);
         }
-        const uint64_t need = r.len + (r.out_d != r.in_d ? r.len : 0) + r.aad_len;
+        const uint64_t need = r.len + (r.out_d != r.in_d ? r.len : 0) + r.aad_len + batch_overhead_bound(r.aad_len, r.len);
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stopping)
             return fail(GCM_E_ARG, "gcm_serve_submit: server is stopping");
@@ -415,12 +485,15 @@ static int report(gcm_serve *s, uint64_t id, int *done, int *accept, uint64_t *l
     if (done)
         *done = st.state == 2;
     if (st.state == 2) {
+        const int status = st.status;
         if (accept)
             *accept = st.accept;
         if (latency_ns)
             *latency_ns = (uint64_t)(st.t_done - st.t_submit);
         if (consume)
             s->reqs.erase(it);
+        if (status != GCM_OK)
+            return fail(status, "request %llu: its batch failed: %s", (unsigned long long)id, s->error_msg);
     }
     return GCM_OK;
 }
@@ -489,6 +562,7 @@ extern "C" int gcm_serve_get_stats(gcm_serve *s, gcm_serve_stats *out)
         out->submitted = s->submitted;
         out->completed = s->completed;
         out->rejected = s->rejected;
+        out->failed = s->failed;
         out->batches = s->batches;
         out->bytes_completed = s->bytes_done;
         out->budget_high_water = s->policy.high_water();

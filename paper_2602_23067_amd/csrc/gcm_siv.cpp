@@ -31,12 +31,24 @@ constexpr uint64_t kSivMax = 1ull << 36;  // P_MAX = A_MAX = 2^36 bytes
 constexpr uint64_t kSivStateOff = kSlotBytes;         // 16 B POLYVAL-as-GHASH value, then 16 B counter block
 constexpr uint64_t kSivTilesOff = kSlotBytes + 256;   // counters and partials
 
-uint64_t siv_tiles(const gcm_ctx *ctx, uint64_t len, uint64_t aad_len, uint32_t *log2B, uint32_t *waves,
-                   uint32_t *gpc)
+// GCM-SIV's tile kernels take the untuned single-message shape (the
+// autotuner times GCM's kernels, not these); explicit gcm_set_launch
+// settings apply.
+Shape siv_shape(const gcm_ctx *ctx, uint64_t m)
 {
-    const uint64_t m = (aad_len + 15) / 16 + (len + 15) / 16 + 1;
-    launch_shape(ctx, m, log2B, waves, gpc);
-    return (m + (1ull << *log2B) - 1) >> *log2B;
+    Shape sh;
+    sh.waves = ctx->cfg_waves ? ctx->cfg_waves : 16;
+    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)sh.waves);
+    sh.log2B = ctx->cfg_log2B ? ctx->cfg_log2B : heuristic_log2B(m, (uint64_t)ctx->cu_count * sh.gpc * sh.waves);
+    sh.fanin = ctx->cfg_fanin ? ctx->cfg_fanin : 2;
+    return sh;
+}
+
+uint64_t siv_tiles(const gcm_ctx *ctx, uint64_t len, uint64_t aad_len, Shape *sh)
+{
+    const uint64_t m = ghash_blocks(aad_len, len);
+    *sh = siv_shape(ctx, m);
+    return (m + (1ull << sh->log2B) - 1) >> sh->log2B;
 }
 
 int launch_siv_pass(gcm_ctx *ctx, int pass, const MsgDesc &d, uint32_t waves, uint32_t gpc, void *partials,
@@ -63,9 +75,11 @@ int siv_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *nonce, s
     if (len > kSivMax || aad_len > kSivMax)
         return fail(GCM_E_TOOLONG, "len %llu / aad_len %llu beyond the 2^36-byte limits",
                     (unsigned long long)len, (unsigned long long)aad_len);
-    int rc = check_buffers(aad_len, len, aad_d, in_d, out_d);
-    if (rc)
-        return rc;
+    PlanError err;
+    if (check_buffers((uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d, 16,
+                      (uint64_t)ok_d, &err))
+        return plan_error(err);
+    int rc = GCM_OK;
     if ((uintptr_t)ws & 255)
         return fail(GCM_E_ARG, "workspace must be 256-byte aligned");
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -74,8 +88,9 @@ int siv_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *nonce, s
     const uint32_t nr = ctx->slot_nr[slot];
     if (nr != 10 && nr != 14)
         return fail(GCM_E_KEYLEN, "GCM-SIV key-generating keys are 16 or 32 bytes");
-    uint32_t log2B, waves, gpc;
-    const uint64_t T = siv_tiles(ctx, len, aad_len, &log2B, &waves, &gpc);
+    Shape sh;
+    const uint64_t T = siv_tiles(ctx, len, aad_len, &sh);
+    const uint32_t log2B = sh.log2B, waves = sh.waves, gpc = sh.gpc;
     const uint64_t need = kSivTilesOff + workspace_bytes_for(T, 1);
     if (ws_bytes < need)
         return fail(GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
@@ -104,7 +119,7 @@ int siv_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *nonce, s
     rc = launch_siv_pass(ctx, op == 0 ? 0 : 2, d, waves, gpc, partials, s);
     if (rc)
         return rc;
-    e = launch_combine(nullptr, 1, &d, partials, counters, s);
+    e = launch_combine(nullptr, 1, &d, partials, counters, sh.fanin, s);
     if (e == hipSuccess)
         e = launch_siv_tag(mslot, gval, nonce, op == 0 ? tag_d : nullptr, ctr, op == 1 ? tag_d : nullptr, ok_d,
                            counters, ctx->d_tables, ctx->d_tables + 256, s);
@@ -121,8 +136,8 @@ int siv_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *nonce, s
     if (len == 0)
         return GCM_OK;
     // encrypt: counter mode from the tag, over the data blocks alone
-    uint32_t cl, cw, cg;
-    launch_shape(ctx, (len + 15) / 16 + 1, &cl, &cw, &cg);
+    const Shape cs = siv_shape(ctx, (len + 15) / 16 + 1);
+    const uint32_t cl = cs.log2B, cw = cs.waves, cg = cs.gpc;
     MsgDesc dc;
     fill_desc(&dc, 2, zero_iv, 0, 0, (uint64_t)in_d, (uint64_t)out_d, len, 0, 0, mslot, nr, cl, cw, 0);
     dc.j0 = (uint64_t)ctr;
@@ -137,8 +152,8 @@ extern "C" uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t 
         if (!ctx)
             return 0;
         std::lock_guard<std::mutex> g(ctx->mu);
-        uint32_t log2B, waves, gpc;
-        const uint64_t T = siv_tiles(ctx, len, aad_len, &log2B, &waves, &gpc);
+        Shape sh;
+        const uint64_t T = siv_tiles(ctx, len, aad_len, &sh);
         return kSivTilesOff + workspace_bytes_for(T, 1);
     GCM_ABI_CATCH_VALUE(0)
 }

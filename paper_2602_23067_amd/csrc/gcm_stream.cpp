@@ -58,8 +58,9 @@ static int run_segment(gcm_stream *st, const MsgDesc &base, hipStream_t s)
 {
     gcm_ctx *ctx = st->ctx;
     MsgDesc d = base;
-    uint32_t log2B, waves, gpc;
-    launch_shape(ctx, d.m, &log2B, &waves, &gpc);
+    // the single-message shape for a message of this segment's blocks
+    const Shape sh = message_shape(ctx, (st->nr - 6) * 4, d.m * 16, 0);
+    const uint32_t log2B = sh.log2B, waves = sh.waves;
     const uint64_t B = 1ull << log2B;
     d.log2B = log2B;
     d.n_tiles = (d.m + B - 1) / B;
@@ -70,12 +71,12 @@ static int run_segment(gcm_stream *st, const MsgDesc &base, hipStream_t s)
     int rc = stream_ws(st, workspace_bytes_for(d.n_tiles, 1));
     if (rc)
         return rc;
-    rc = launch_tile_range(ctx, d, waves, gpc, st->ws, s);
+    rc = launch_tile_range(ctx, d, sh, st->ws, s);
     if (rc)
         return rc;
     uint32_t *counters = reinterpret_cast<uint32_t *>(st->ws);
     const uint8_t *partials = reinterpret_cast<const uint8_t *>(st->ws) + workspace_counter_bytes(1);
-    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, s);
+    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, sh.fanin, s);
     if (e != hipSuccess)
         return fail_hip(e, "combine launch");
     return GCM_OK;

@@ -3,12 +3,14 @@
 // in a CPU-only test harness.
 //
 // Requests wait in arrival order.  A request is admitted when the bytes it
-// needs on the device (its input, output and AAD) fit in what is left of the
-// HBM budget; admission never skips ahead of an earlier request, so no
-// request starves.  Admitted requests are handed out in arrival order as
-// batches of at most max_batch_reqs requests and about max_batch_bytes of
-// payload (a single larger request forms a batch of its own).  Completing a
-// request returns its bytes to the budget.
+// needs on the device (its input, output and AAD, plus its share of a
+// batch's descriptors, work list and tile partials) fit in what is left of
+// the HBM budget after the serving loop's own retained scratch (`slack`:
+// stream-slot memory not used by a running batch); admission never skips
+// ahead of an earlier request, so no request starves.  Admitted requests are
+// handed out in arrival order as batches of at most max_batch_reqs requests
+// and about max_batch_bytes of payload (a single larger request forms a batch
+// of its own).  Completing a request returns its bytes to the budget.
 #pragma once
 #include <cstdint>
 #include <deque>
@@ -49,10 +51,11 @@ class ServePolicy {
     size_t admit(std::vector<uint64_t> *admitted = nullptr)
     {
         size_t k = 0;
-        while (!pending_.empty() && admitted_ + pending_.front().need <= cfg_.budget) {
+        while (!pending_.empty() && slack_ <= cfg_.budget && admitted_ <= cfg_.budget - slack_ &&
+               pending_.front().need <= cfg_.budget - slack_ - admitted_) {
             admitted_ += pending_.front().need;
-            if (admitted_ > high_)
-                high_ = admitted_;
+            if (admitted_ + slack_ > high_)
+                high_ = admitted_ + slack_;
             if (admitted)
                 admitted->push_back(pending_.front().id);
             ready_.push_back(pending_.front());
@@ -80,6 +83,16 @@ class ServePolicy {
 
     void complete(uint64_t need) { admitted_ -= need; }
 
+    // Device bytes the serving loop retains beyond what admitted requests
+    // account for (counted against the budget).
+    void set_slack(uint64_t bytes)
+    {
+        slack_ = bytes;
+        if (admitted_ + slack_ > high_)
+            high_ = admitted_ + slack_;
+    }
+    uint64_t slack() const { return slack_; }
+
     uint64_t admitted_bytes() const { return admitted_; }
     uint64_t high_water() const { return high_; }
     size_t pending() const { return pending_.size(); }
@@ -89,7 +102,7 @@ class ServePolicy {
   private:
     PolicyConfig cfg_;
     std::deque<PolicyReq> pending_, ready_;
-    uint64_t admitted_ = 0, high_ = 0;
+    uint64_t admitted_ = 0, high_ = 0, slack_ = 0;
 };
 
 }  // namespace gcm

@@ -60,7 +60,7 @@ class ServeConfig(ctypes.Structure):
 class ServeStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "batches", "bytes_completed",
                                                "budget_high_water", "overlapped_admissions",
-                                               "max_inflight_batches")] + \
+                                               "max_inflight_batches", "failed")] + \
                [(n, ctypes.c_double) for n in ("p50_ms", "p99_ms", "mean_ms", "max_ms", "wall_s")]
 
     def as_dict(self):
@@ -69,7 +69,8 @@ class ServeStats(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("log2_tile_blocks", ctypes.c_uint32), ("waves_per_group", ctypes.c_uint32),
-                ("candidates", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("gbs", ctypes.c_double)]
+                ("candidates", ctypes.c_uint32), ("best_ms", ctypes.c_float), ("gbs", ctypes.c_double),
+                ("groups_per_cu", ctypes.c_uint32), ("combine_fanin", ctypes.c_uint32)]
 
 
 class Job(ctypes.Structure):
@@ -141,6 +142,8 @@ def load() -> ctypes.CDLL:
         "gcm_serve_get_stats": ([vp, vp], ctypes.c_int),
         "gcm_serve_stop": ([vp], ctypes.c_int),
         "gcm_autotune": ([vp, u32, u64, u32, vp, vp], ctypes.c_int),
+        "gcm_batch_autotune": ([vp, vp, u32, vp, u64, u32, vp, vp], ctypes.c_int),
+        "gcm_set_combine": ([vp, u32], ctypes.c_int),
         "gcm_autotune_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_autotune_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
@@ -458,8 +461,7 @@ class Context:
     def autotune(self, key_len: int, length: int, reps: int = 3, stream=None) -> dict:
         r = TuneResult()
         _check(load().gcm_autotune(self._h, key_len, length, reps, ctypes.byref(r), _stream(stream)))
-        return {"log2_tile_blocks": r.log2_tile_blocks, "waves_per_group": r.waves_per_group,
-                "candidates": r.candidates, "best_ms": r.best_ms, "gbs": r.gbs}
+        return _tune_dict(r)
 
     def autotune_save(self, path: str) -> None:
         _check(load().gcm_autotune_save(self._h, path.encode()))
@@ -469,6 +471,23 @@ class Context:
 
     def set_launch(self, log2_tile_blocks: int = 0, waves_per_group: int = 0, groups_per_cu: int = 0) -> None:
         _check(load().gcm_set_launch(self._h, log2_tile_blocks, waves_per_group, groups_per_cu))
+
+    def set_combine(self, fanin: int = 0) -> None:
+        _check(load().gcm_set_combine(self._h, fanin))
+
+    def batch_autotune(self, jobs, base, reps: int = 3, stream=None) -> dict:
+        """Launch-shape search on a batch (see gcm_batch_autotune); `jobs` and
+        `base` as for Batch."""
+        r = TuneResult()
+        _check(load().gcm_batch_autotune(self._h, ctypes.cast(jobs, ctypes.c_void_p), len(jobs), _dev(base),
+                                         base.numel(), reps, ctypes.byref(r), _stream(stream)))
+        return _tune_dict(r)
+
+
+def _tune_dict(r: TuneResult) -> dict:
+    return {"log2_tile_blocks": r.log2_tile_blocks, "waves_per_group": r.waves_per_group,
+            "candidates": r.candidates, "best_ms": r.best_ms, "gbs": r.gbs, "groups_per_cu": r.groups_per_cu,
+            "combine_fanin": r.combine_fanin}
 
 
 def fits_nonce() -> bytes:

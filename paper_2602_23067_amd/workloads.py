@@ -223,3 +223,64 @@ def serving_key_table(seed: int, n_keys: int = 1024):
     """Resident key table: half AES-128, half AES-256."""
     r = rng_for(seed, 5, 1)
     return [random_bytes(r, 16 if i % 2 == 0 else 32).tobytes() for i in range(n_keys)]
+
+
+def fits_noise_bytes(rng: np.random.Generator, nbytes: int, mean: float = 1000.0, sigma: float = 30.0) -> np.ndarray:
+    """`nbytes` (a multiple of 4) of big-endian float32 Gaussian sky noise,
+    the pixel content of a FITS-shaped request without point sources."""
+    assert nbytes % 4 == 0
+    img = rng.standard_normal(size=nbytes // 4, dtype=np.float32)
+    img *= np.float32(sigma)
+    img += np.float32(mean)
+    return img.astype(">f4").view(np.uint8)
+
+
+@dataclass
+class ServingCase:
+    op: int            # 0 encrypt, 1 decrypt-verify
+    key_index: int     # index into serving_key_table
+    iv: bytes
+    size: int          # payload bytes (a multiple of 2880)
+    tamper: Optional[tuple] = None  # decrypt only: ("tag"|"ct", fraction, bit)
+
+
+def serving_parity_spec(seed: int = 2602, n: int = 48, big: int = 256 << 20, cap: int = 96 << 20,
+                        n_keys: int = 1024, tamper_frac: float = 0.2) -> List[ServingCase]:
+    """Requests drawn from the serving workload's distribution (lognormal
+    sizes, median 4 MiB, sigma ln(2^16)/6, clipped to [16 KiB, 1 GiB] and
+    rounded up to 2880 multiples; 50/50 encrypt / decrypt-verify; keys uniform
+    over the resident table), bounded for a parity test: request 0 is an
+    encrypt and request 1 a decrypt-verify of at least `big` bytes, the
+    others are capped at `cap` bytes; about `tamper_frac` of the decrypts
+    carry one flipped tag or ciphertext bit."""
+    r = rng_for(seed, 5, 7)
+    sizes = lognormal_lengths(r, n, float(4 << 20), float(np.log(2 ** 16) / 6), 16 << 10, 1 << 30)
+    sizes = np.minimum(sizes, cap)
+    big_pad = (big + FITS_BLOCK - 1) // FITS_BLOCK * FITS_BLOCK
+    sizes[0] = big_pad
+    sizes[1] = big_pad
+    sizes = (sizes + FITS_BLOCK - 1) // FITS_BLOCK * FITS_BLOCK
+    ops = r.integers(0, 2, n)
+    ops[0], ops[1] = 0, 1
+    kidx = r.integers(0, n_keys, n)
+    cases = []
+    for i in range(n):
+        iv = random_bytes(r, 12).tobytes()
+        tamper = None
+        if ops[i] == 1 and (i == 3 or r.random() < tamper_frac):
+            tamper = ("tag" if r.random() < 0.5 else "ct", float(r.random()), int(r.integers(0, 8)))
+        cases.append(ServingCase(int(ops[i]), int(kidx[i]), iv, int(sizes[i]), tamper))
+    # request 3 is a tampered decrypt whenever it is a decrypt; make sure at least one exists
+    if not any(c.tamper for c in cases):
+        for c in cases:
+            if c.op == 1:
+                c.tamper = ("tag", 0.5, 3)
+                break
+    return cases
+
+
+def serving_case_data(seed: int, i: int, case: ServingCase):
+    """(header AAD, FITS-shaped payload) of serving parity request i."""
+    r = rng_for(seed, 5, 8, i)
+    aad = np.frombuffer(fits_header(r), dtype=np.uint8).copy()
+    return aad, fits_noise_bytes(r, case.size)

@@ -67,13 +67,20 @@ int main()
                         held += r.need;
                     }
                 }
-            } else if (!running.empty()) {  // completion of a random running request
+            } else if (!running.empty() && rng() % 8) {  // completion of a random running request
                 const size_t k = rng() % running.size();
                 held -= running[k].need;
+                // the stream slot that ran it keeps part of its scratch: bytes
+                // move from the request's admission to the loop's slack
+                const uint64_t keep = rng() % (running[k].need + 1);
                 p.complete(running[k].need);
+                p.set_slack(p.slack() + keep);
                 running.erase(running.begin() + (long)k);
+            } else {  // the loop frees idle slot memory
+                p.set_slack(rng() % 2 ? 0 : p.slack() / 2);
             }
             CHECK(p.admitted_bytes() <= c.budget);
+            CHECK(p.admitted_bytes() + p.slack() <= c.budget);
             CHECK(p.high_water() <= c.budget);
             CHECK(held <= p.admitted_bytes());
         }
@@ -83,7 +90,8 @@ int main()
         running.clear();
         std::vector<PolicyReq> b;
         for (int guard = 0; guard < 100000 && (p.pending() || p.ready()); ++guard) {
-            p.admit();
+            if (!p.admit() && p.ready() == 0)
+                p.set_slack(0);  // nothing runs and the head does not fit: free idle slot memory
             while (p.next_batch(&b))
                 for (const PolicyReq &r : b)
                     p.complete(r.need);

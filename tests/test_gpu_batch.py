@@ -193,3 +193,34 @@ def test_batch_validation(ctx):
             gcm.Batch(ctx, jobs, base)
     finally:
         ctx.key_release(slot)
+
+
+def test_batch_autotune_then_batches_use_the_tuned_shape(ctx):
+    """The exhaustive batch search (waves x groups per CU x tile cap x
+    fan-in, every point's tags and flags required equal) on a mixed
+    encrypt / decrypt batch; afterwards a batch of that shape is planned with
+    the cached winner and every message still matches the oracle."""
+    n = 36
+    ops = [i % 2 for i in range(n)]
+    plan = {i: t for i, t in workloads.tamper_plan(12, n, frac=0.3).items() if ops[i] == 1}
+    p = Packed(ctx, 13, n, median=30_000, lo=1, hi=400_000, ops=ops, tamper=plan)
+    res = ctx.batch_autotune(p.jobs, p.base, reps=1)
+    print("batch autotune:", res, flush=True)
+    assert res["candidates"] >= 3 * 5 * 4
+    assert res["waves_per_group"] in (8, 12, 16) and 8 <= res["log2_tile_blocks"] <= 12
+    assert res["combine_fanin"] in (2, 4, 8, 16)
+    assert p.check() == set(plan)  # the outputs of the last point searched
+    p.reset_device()
+    b = gcm.Batch(ctx, p.jobs, p.base)
+    b.graph_launch()
+    assert p.check() == set(plan)
+    b.close()
+    p.release(ctx)
+
+
+def test_batch_autotune_rejects_in_place_jobs(ctx):
+    p = Packed(ctx, 14, 4, median=2_000, lo=16, hi=4_000, in_place=True)
+    with pytest.raises(gcm.GcmError) as e:
+        ctx.batch_autotune(p.jobs, p.base, reps=1)
+    assert e.value.code == gcm.GCM_E_ARG
+    p.release(ctx)

@@ -217,7 +217,8 @@ def test_autotune_picks_a_shape_and_results_stay_exact(ctx, tmp_path):
     oracle; the cache survives a save/load round trip."""
     res = ctx.autotune(32, 3 << 20, reps=2)
     print("autotune:", res, flush=True)
-    assert res["candidates"] >= 2 and res["waves_per_group"] in (8, 16) and 8 <= res["log2_tile_blocks"] <= 14
+    assert res["candidates"] >= 2 and res["waves_per_group"] in (8, 12, 16) and 8 <= res["log2_tile_blocks"] <= 14
+    assert res["combine_fanin"] in (2, 4, 8, 16) and res["groups_per_cu"] >= 1
     r = workloads.rng_for(37)
     key, iv = workloads.random_bytes(r, 32).tobytes(), workloads.random_bytes(r, 12).tobytes()
     _check_case(ctx, key, iv, workloads.random_bytes(r, 50), workloads.random_bytes(r, (3 << 20) + 5))
@@ -234,3 +235,68 @@ def test_autotune_picks_a_shape_and_results_stay_exact(ctx, tmp_path):
         assert c2.encrypt(key2, iv, None, pt_d, ct_d) == rtag and np.array_equal(host(ct_d), rct)
     finally:
         c2.close()
+
+
+def test_workspace_size_covers_every_tuned_shape(ctx):
+    """gcm_workspace_size and the asynchronous calls plan with the same shape
+    function: after autotuning every key size at a message size, a workspace
+    of exactly gcm_workspace_size bytes is enough for each key size, and the
+    results match the oracle."""
+    n = (1 << 20) + 3
+    for kb in (16, 24, 32):
+        ctx.autotune(kb, n, reps=1)
+    r = workloads.rng_for(41)
+    aad = workloads.random_bytes(r, 40)
+    pt = workloads.random_bytes(r, n)
+    ws = torch.zeros(ctx.workspace_size(n, aad.size), dtype=torch.uint8, device="cuda")
+    for kb in (16, 24, 32):
+        key, iv = workloads.random_bytes(r, kb).tobytes(), workloads.random_bytes(r, 12).tobytes()
+        slot = ctx.key_register(key)
+        try:
+            rct, rtag = oracle.gcm_encrypt(key, iv, aad, pt)
+            pt_d, aad_d = to_dev(pt), to_dev(aad)
+            ct_d = torch.empty_like(pt_d)
+            tag_d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+            ctx.encrypt_async(slot, iv, aad_d, pt_d, ct_d, tag_d, ws)
+            assert bytes(host(tag_d)) == rtag and np.array_equal(host(ct_d), rct)
+        finally:
+            ctx.key_release(slot)
+
+
+@pytest.mark.parametrize("fanin", [2, 4, 8, 16])
+def test_reduction_fanin_does_not_change_results(ctx, fanin):
+    """The tree over tile partials gives the same tag for every fan-in, with
+    tile counts that are not powers of the fan-in, span one and several tree
+    levels, and exceed the 1024 leaves (the strided Horner before the tree)."""
+    r = workloads.rng_for(43, fanin)
+    try:
+        ctx.set_combine(fanin)
+        for log2B, n in ((6, 16 * 64 * 5 + 7), (6, 16 * 64 * 37), (6, 16 * 64 * 300 + 1), (8, 16 * 256 * 1500 + 9)):
+            ctx.set_launch(log2B, 16, 0)
+            key, iv = workloads.random_bytes(r, 32).tobytes(), workloads.random_bytes(r, 12).tobytes()
+            _check_case(ctx, key, iv, workloads.random_bytes(r, 33), workloads.random_bytes(r, n))
+    finally:
+        ctx.set_combine(0)
+        ctx.set_launch(0, 0, 0)
+
+
+def test_output_may_not_overlap_aad_tag_or_flag(ctx):
+    slot = ctx.key_register(bytes(16))
+    try:
+        buf = torch.zeros(4096, dtype=torch.uint8, device="cuda")
+        ws = torch.zeros(ctx.workspace_size(1024, 256), dtype=torch.uint8, device="cuda")
+        with pytest.raises(gcm.GcmError) as e:  # ciphertext over the AAD
+            ctx.encrypt_async(slot, bytes(12), buf[0:256], buf[1024:2048], buf[128:1152], buf[3000:3016], ws)
+        assert e.value.code == gcm.GCM_E_ALIAS
+        with pytest.raises(gcm.GcmError) as e:  # ciphertext over the tag
+            ctx.encrypt_async(slot, bytes(12), None, buf[0:1024], buf[2048:3072], buf[2560:2576], ws)
+        assert e.value.code == gcm.GCM_E_ALIAS
+        ok = torch.zeros(1, dtype=torch.int32, device="cuda")
+        with pytest.raises(gcm.GcmError) as e:  # plaintext over the expected tag
+            ctx.decrypt_verify_async(slot, bytes(12), None, buf[0:1024], buf[1024:1040], buf[1024:2048], ok, ws)
+        assert e.value.code == gcm.GCM_E_ALIAS
+        with pytest.raises(gcm.GcmError) as e:  # one-shot: ciphertext over the AAD
+            ctx.encrypt(bytes(16), bytes(12), buf[0:256], buf[1024:2048], buf[0:1024])
+        assert e.value.code == gcm.GCM_E_ALIAS
+    finally:
+        ctx.key_release(slot)

@@ -130,3 +130,37 @@ def test_serving_rejects_oversize_and_bad_slot(ctx):
     finally:
         srv.stop()
         ctx.key_release(slot)
+
+
+def test_serving_batch_that_cannot_launch_fails_closed():
+    """A batch whose device scratch cannot be allocated (the context's own
+    memory budget is exhausted) completes its requests with that status: the
+    wait reports GCM_E_NOMEM, a decrypt is never accepted, and the stats count
+    the requests as completed and failed."""
+    # budget: the context's tables, Frobenius tables and two key slots, and
+    # nothing for the serving loop's per-batch scratch
+    slot_bytes = 2048 + 65536 + 40 * 8192 + 16384
+    budget = 2 * 256 * 4 + 47 * 4096 * 16 + 2 * slot_bytes + 256
+    c = gcm.Context(device=0, hbm_budget=budget, key_slots=2)
+    try:
+        key, iv = bytes(range(16)), bytes(12)
+        slot = c.key_register(key)
+        pt = workloads.random_bytes(workloads.rng_for(58), 4096)
+        ct, tag = oracle.gcm_encrypt(key, iv, b"", pt)
+        x = torch.from_numpy(ct).cuda()
+        y = torch.full_like(x, 0x5A)
+        t = torch.from_numpy(np.frombuffer(tag, np.uint8).copy()).cuda()
+        srv = gcm.Server(c, n_streams=1, hbm_budget=1 << 20)
+        try:
+            rid = srv.submit(1, slot, iv, None, x, y, t)  # a valid tag: would be accepted
+            with pytest.raises(gcm.GcmError) as e:
+                srv.wait(rid)
+            assert e.value.code == gcm.GCM_E_NOMEM
+            st = srv.stats()
+            assert st["completed"] == 1 and st["failed"] == 1 and st["rejected"] == 0
+        finally:
+            with pytest.raises(gcm.GcmError) as e:  # stop reports the loop's error
+                srv.stop()
+            assert e.value.code == gcm.GCM_E_NOMEM
+    finally:
+        c.close()
