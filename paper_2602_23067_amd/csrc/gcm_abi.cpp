@@ -485,9 +485,9 @@ int gcm::ensure_ws_locked(gcm_ctx *ctx, uint64_t bytes)
 
 // ---------------------------------------------------------------- async entry points
 
-static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
-                        const uint8_t *aad_d, uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d,
-                        const uint8_t *tag_d, int32_t *ok_d, void *ws, uint64_t ws_bytes, void *stream)
+int gcm::async_launch(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                      const uint8_t *aad_d, uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d,
+                      const uint8_t *tag_d, int32_t *ok_d, void *ws, uint64_t ws_bytes, bool fit_ws, void *stream)
 {
     if (!ctx || !iv || !tag_d || (op == 1 && !ok_d) || !ws)
         return fail(GCM_E_ARG, "NULL argument");
@@ -501,12 +501,16 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     std::lock_guard<std::mutex> g(ctx->mu);
     if (slot >= ctx->n_slots || !ctx->slot_used[slot])
         return fail(GCM_E_SLOT, "key slot %u is not registered", slot);
-    const Shape sh = message_shape(ctx, (ctx->slot_nr[slot] - 6) * 4, len, aad_len);
+    Shape sh = message_shape(ctx, (ctx->slot_nr[slot] - 6) * 4, len, aad_len);
+    const uint64_t m = ghash_blocks(aad_len, len);
+    if (fit_ws)  // larger tiles (fewer partials) until the workspace holds them; results do not change
+        while (sh.log2B < kFitMaxLog2B && workspace_bytes_for((m + (1ull << sh.log2B) - 1) >> sh.log2B, 1) > ws_bytes)
+            ++sh.log2B;
     MsgDesc d;
     fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
               (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), ctx->slot_nr[slot], sh.log2B, sh.waves, 0);
     if (ws_bytes < workspace_bytes_for(d.n_tiles, 1))
-        return fail(GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+        return fail(fit_ws ? GCM_E_NOMEM : GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
                     (unsigned long long)ws_bytes, (unsigned long long)workspace_bytes_for(d.n_tiles, 1));
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
@@ -515,7 +519,13 @@ static int async_common(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t 
     rc = set_iv(&d, iv, iv_len, ws, s);
     if (rc)
         return rc;
-    return launch_single(ctx, d, sh, ws, s);
+    // a fitted workspace is the no-allocation path: no profiling events there
+    const bool prof = ctx->prof;
+    if (fit_ws)
+        ctx->prof = false;
+    rc = launch_single(ctx, d, sh, ws, s);
+    ctx->prof = prof;
+    return rc;
 }
 
 extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
@@ -523,8 +533,8 @@ extern "C" int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv,
                                  void *workspace_d, uint64_t workspace_bytes, void *stream)
 {
     GCM_ABI_TRY
-        return async_common(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
-                            workspace_bytes, stream);
+        return async_launch(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr, workspace_d,
+                            workspace_bytes, false, stream);
     GCM_ABI_CATCH
 }
 
@@ -534,8 +544,8 @@ extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8
                                         uint64_t workspace_bytes, void *stream)
 {
     GCM_ABI_TRY
-        return async_common(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
-                            workspace_bytes, stream);
+        return async_launch(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
+                            workspace_bytes, false, stream);
     GCM_ABI_CATCH
 }
 

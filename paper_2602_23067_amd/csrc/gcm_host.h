@@ -118,6 +118,16 @@ bool valid_iv_len(size_t n);
 // of workspace `ws` (after its partials and E_K(J0)), and points d.j0 there.
 int set_iv(MsgDesc *d, const uint8_t *iv, size_t iv_len, void *ws, hipStream_t s);
 int launch_single(gcm_ctx *ctx, const MsgDesc &d, const Shape &sh, void *ws, hipStream_t s);
+// The asynchronous single-message path (gcm_encrypt_async /
+// gcm_decrypt_verify_async): validate, plan with message_shape and enqueue
+// on `stream` with the caller's workspace.  With fit_ws (the no-allocation
+// path) the tile size is raised (up to 2^kFitMaxLog2B blocks) until the
+// partials fit in ws_bytes, a message that still does not fit is
+// GCM_E_NOMEM, and no profiling events are recorded.
+constexpr uint32_t kFitMaxLog2B = 16;
+int async_launch(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
+                 uint64_t aad_len, const uint8_t *in_d, uint64_t len, uint8_t *out_d, const uint8_t *tag_d,
+                 int32_t *ok_d, void *ws, uint64_t ws_bytes, bool fit_ws, void *stream);
 // batches (gcm_batch.cpp; caller holds ctx->mu): validate and plan jobs
 // (with `forced` as the shape if non-NULL), create a batch, enqueue its
 // kernels, free it

@@ -617,12 +617,10 @@ __device__ __forceinline__ u32x4 wave_xor_reduce(u32x4 a)
 constexpr uint32_t kTeBase = 0x10000u;
 
 struct LaneK {
-    uint32_t sel[4];   // v_perm selectors: byte u_r of the state word into bits 8..15
-    uint32_t off[4];   // 0x10000 | 64*u_r + 4*copy            (rounds 1..Nr-1)
-    uint32_t offl[4];  // 0x10000 | 64*((u_r+2)&3) + 4*copy    (last round)
-    uint32_t mask[4];  // 0xff << 8*u_r                         (last round)
-    uint32_t rot;      // alignbit shift for rotl by 8g
-    uint32_t unrot;    // alignbit shift for rotr by 8g
+    uint32_t sel[4];          // v_perm selectors: byte u_r of the state word into bits 8..15
+    uint32_t off[4];          // 0x10000 | 64*u_r + 4*copy
+    uint32_t rot;             // alignbit shift for rotl by 8g
+    uint32_t fsel01, fsel23;  // last round: v_perm selectors of the S-box bytes
 };
 
 __device__ __forceinline__ LaneK lane_constants(int lane)
@@ -634,11 +632,14 @@ __device__ __forceinline__ LaneK lane_constants(int lane)
         const uint32_t u = ((uint32_t)r + g) & 3u;
         k.sel[r] = 0x0c020000u | ((4u + u) << 8);
         k.off[r] = kTeBase | (u * 64u + copy * 4u);
-        k.offl[r] = kTeBase | (((u + 2u) & 3u) * 64u + copy * 4u);
-        k.mask[r] = 0xffu << (8u * u);
+    }
+    {
+        const uint32_t u0 = g & 3u, u1 = (1u + g) & 3u, u2 = (2u + g) & 3u, u3 = (3u + g) & 3u;
+        // S(x) sits in byte (u+1)&3 of table u
+        k.fsel01 = ((u0 + 1u) & 3u) | ((4u + ((u1 + 1u) & 3u)) << 8) | 0x0c0c0000u;
+        k.fsel23 = 0x00000c0cu | (((u2 + 1u) & 3u) << 16) | ((4u + ((u3 + 1u) & 3u)) << 24);
     }
     k.rot = (32u - 8u * g) & 31u;
-    k.unrot = 8u * g;
     return k;
 }
 
@@ -660,11 +661,7 @@ __device__ __forceinline__ uint32_t te_u(const uint8_t *lds, uint32_t t, uint32_
     return lds_word(lds, kTeBase + x * 256u + t * 64u);
 }
 
-// bits of a where m is set, bits of b elsewhere
-__device__ __forceinline__ uint32_t bsel(uint32_t m, uint32_t a, uint32_t b) { return (a & m) | (b & ~m); }
-
 #define LK(r, w) lds_word(lds, __builtin_amdgcn_perm((w), lk.off[r], lk.sel[r]))
-#define LL(r, w) lds_word(lds, __builtin_amdgcn_perm((w), lk.offl[r], lk.sel[r]))
 
 struct AesCtx {
     uint32_t u0, u1, u2, u3;  // round-1 columns with the 12 IV bytes folded in (unrotated, uniform)
@@ -677,9 +674,9 @@ template <int R0, int NR>
 __device__ __forceinline__ u32x4 aes_rounds(uint32_t s0, uint32_t s1, uint32_t s2, uint32_t s3,
                                             const CONST_AS uint32_t *rk, const uint8_t *lds, const LaneK &lk)
 {
-    // rounds stay a loop: each depends on the last, and the smaller code
-    // measured slightly faster than the unrolled form
-#pragma unroll 1
+    // fully unrolled: the scheduler issues each round's lookups as soon as
+    // their addresses exist, across round boundaries
+#pragma unroll
     for (int r = R0; r < NR; ++r) {
         const uint32_t k0 = rotr_by(rk[4 * r + 0], lk.rot), k1 = rotr_by(rk[4 * r + 1], lk.rot);
         const uint32_t k2 = rotr_by(rk[4 * r + 2], lk.rot), k3 = rotr_by(rk[4 * r + 3], lk.rot);
@@ -692,14 +689,18 @@ __device__ __forceinline__ u32x4 aes_rounds(uint32_t s0, uint32_t s1, uint32_t s
         s2 = t2;
         s3 = t3;
     }
-    // last round: S-box bytes only; table (u+2)&3 holds S(x) in byte u
-    const uint32_t k0 = rotr_by(rk[4 * NR + 0], lk.rot), k1 = rotr_by(rk[4 * NR + 1], lk.rot);
-    const uint32_t k2 = rotr_by(rk[4 * NR + 2], lk.rot), k3 = rotr_by(rk[4 * NR + 3], lk.rot);
-    const uint32_t o0 = bsel(lk.mask[0], LL(0, s0), bsel(lk.mask[1], LL(1, s1), bsel(lk.mask[2], LL(2, s2), LL(3, s3)))) ^ k0;
-    const uint32_t o1 = bsel(lk.mask[0], LL(0, s1), bsel(lk.mask[1], LL(1, s2), bsel(lk.mask[2], LL(2, s3), LL(3, s0)))) ^ k1;
-    const uint32_t o2 = bsel(lk.mask[0], LL(0, s2), bsel(lk.mask[1], LL(1, s3), bsel(lk.mask[2], LL(2, s0), LL(3, s1)))) ^ k2;
-    const uint32_t o3 = bsel(lk.mask[0], LL(0, s3), bsel(lk.mask[1], LL(1, s0), bsel(lk.mask[2], LL(2, s1), LL(3, s2)))) ^ k3;
-    return u32x4{rotr_by(o0, lk.unrot), rotr_by(o1, lk.unrot), rotr_by(o2, lk.unrot), rotr_by(o3, lk.unrot)};
+    // last round: the round tables hold S(x) in byte (u+1)&3; two v_perm
+    // pick the four S-box bytes into their unrotated positions, so the key
+    // is added unrotated and the result needs no rotation back
+    const uint32_t o0 = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_perm(LK(1, s1), LK(0, s0), lk.fsel01),
+                                                    __builtin_amdgcn_perm(LK(3, s3), LK(2, s2), lk.fsel23), rk[4 * NR + 0], 0x56);
+    const uint32_t o1 = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_perm(LK(1, s2), LK(0, s1), lk.fsel01),
+                                                    __builtin_amdgcn_perm(LK(3, s0), LK(2, s3), lk.fsel23), rk[4 * NR + 1], 0x56);
+    const uint32_t o2 = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_perm(LK(1, s3), LK(0, s2), lk.fsel01),
+                                                    __builtin_amdgcn_perm(LK(3, s1), LK(2, s0), lk.fsel23), rk[4 * NR + 2], 0x56);
+    const uint32_t o3 = __builtin_amdgcn_bitop3_b32(__builtin_amdgcn_perm(LK(1, s0), LK(0, s3), lk.fsel01),
+                                                    __builtin_amdgcn_perm(LK(3, s2), LK(2, s1), lk.fsel23), rk[4 * NR + 3], 0x56);
+    return u32x4{o0, o1, o2, o3};
 }
 
 // Keystream block for counter value `ctr` (big-endian in bytes 12..15).
