@@ -111,7 +111,7 @@ extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_byt
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
         ctx->cu_count = cus > 0 ? cus : 1;
 
-        int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), 2 * 256 * sizeof(uint32_t));
+        int rc = ctx_alloc(ctx, reinterpret_cast<void **>(&ctx->d_tables), kAesTableWords * sizeof(uint32_t));
         if (rc == GCM_OK)
             rc = ctx_alloc(ctx, &ctx->d_frob, frob_table_bytes());
         if (rc == GCM_OK)
@@ -149,7 +149,7 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
             return fail(GCM_E_ARG, "gcm_ctx_destroy: NULL context");
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
-        ctx_free(ctx, ctx->d_tables, 2 * 256 * sizeof(uint32_t));
+        ctx_free(ctx, ctx->d_tables, kAesTableWords * sizeof(uint32_t));
         ctx_free(ctx, ctx->d_frob, frob_table_bytes());
         ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
         ctx_free(ctx, ctx->d_io, 256);

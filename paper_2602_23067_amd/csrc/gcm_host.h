@@ -16,7 +16,7 @@ struct gcm_ctx {
     int cu_count = 1;
     uint64_t budget = 0;  // 0 = unbounded
     uint64_t used = 0;
-    uint32_t *d_tables = nullptr;  // TE0[256] then S-box[256] (as words)
+    uint32_t *d_tables = nullptr;  // kAesTableWords: TE0, the S-box (as words), TE1..TE3
     void *d_frob = nullptr;        // Frobenius tables x -> x^(2^k), k = 1..47
     uint8_t *d_slots = nullptr;    // n_slots * kSlotBytes
     uint32_t n_slots = 0;

@@ -15,6 +15,13 @@
 
 namespace gcm {
 
+// ---- AES tables (device memory, one block per context) ----
+// words [0, 256): TE0, the MixColumns column (2s, s, s, 3s) of S(x);
+// [256, 512): the S-box as words; [512, 1280): TE1..TE3 = TE0 rotated left by
+// 8, 16 and 24 bits.
+constexpr uint32_t kTe1Off = 512;
+constexpr uint32_t kAesTableWords = 1280;
+
 // ---- key slot (device memory, one per resident key) ----
 constexpr int kMaxNr = 14;
 constexpr int kPowLevels = 48;      // H^(2^k), k = 0..47

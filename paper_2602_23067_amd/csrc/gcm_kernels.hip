@@ -142,8 +142,13 @@ __global__ void k_init_tables(uint32_t *te0, uint32_t *sbox)
         const uint32_t inv = a ? ex[(255 - lg[a]) % 255] : 0u;
         const uint32_t s = inv ^ rotl8(inv, 1) ^ rotl8(inv, 2) ^ rotl8(inv, 3) ^ rotl8(inv, 4) ^ 0x63u;
         const uint32_t s2 = gf8_xtime(s), s3 = s2 ^ s;
-        te0[a] = s2 | (s << 8) | (s << 16) | (s3 << 24);
+        const uint32_t t0 = s2 | (s << 8) | (s << 16) | (s3 << 24);
+        te0[a] = t0;
         sbox[a] = s;
+        // TE1..TE3 after the S-box (read by the scalar unit, which has no rotate)
+        te0[kTe1Off + a] = rotl32(t0, 8);
+        te0[kTe1Off + 256 + a] = rotl32(t0, 16);
+        te0[kTe1Off + 512 + a] = rotl32(t0, 24);
     }
 }
 
@@ -728,10 +733,11 @@ struct Ctr2 {
     uint32_t v0, v1, v2, v3;
 };
 
-// T_t[x] = rotl(T0[x], 8t) read through the scalar cache (uniform x)
+// T_t[x] read through the scalar cache (uniform x): TE0 at word 0, TE1..TE3
+// from word kTe1Off of the table block
 __device__ __forceinline__ uint32_t te_s(const CONST_AS uint32_t *te, int t, uint32_t x)
 {
-    return rotl32(te[x], 8 * t);
+    return t == 0 ? te[x] : te[kTe1Off + 256 * (t - 1) + x];
 }
 
 // the four round-2 words for upper counter bits `hi` (wave-uniform)
@@ -1018,45 +1024,62 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         }
     }
 
+    // Rows [fa, fb) hold 64 whole data blocks each and take the fast path:
+    // v0 >= na and v0 + 64 <= na + nfull, except a streamed segment's block 0
+    // (v0 == 0), which takes the boundary path that adds the running GHASH
+    // value.  The range is computed once, so the row loop keeps only scalar
+    // 32-bit bookkeeping and one uniform row address.
+    int64_t rf0, rf1;
+    {
+        const int64_t lo = na - vbase;                // 64 r >= lo
+        const int64_t hi = na + nfull - vbase - 64;   // 64 r <= hi
+        rf0 = lo <= 0 ? 0 : (lo + 63) >> 6;
+        rf1 = hi < 0 ? 0 : (hi >> 6) + 1;
+        if (J0DEV && d.ystate && rf0 < rf1 && vbase + 64 * rf0 == 0)
+            ++rf0;
+    }
+    const uint32_t fa = (uint32_t)(rf0 > (int64_t)r ? (rf0 < (int64_t)R ? rf0 : (int64_t)R) : (int64_t)r);
+    const uint32_t fb = (uint32_t)(rf1 > (int64_t)fa ? (rf1 < (int64_t)R ? rf1 : (int64_t)R) : (int64_t)fa);
+    for (; r < fa; ++r)
+        boundary_row(vbase + 64 * (int64_t)r);
+
     uint32_t hc = 0xffffffffu;  // upper counter bits `cur` belongs to (none yet)
     Ctr2 cur = {0, 0, 0, 0};
-    for (; r < R; ++r) {
+    const uint32_t loff = 16u * (uint32_t)lane;  // this lane's byte offset in a row
+    for (; r < fb; ++r) {
         // re-read the round keys with scalar loads each row instead of holding
         // 4*(Nr+1) of them (or their lane-rotated copies) in registers
         rk = rk_base;
         asm volatile("" : "+s"(rk));
-        const int64_t v0 = vbase + 64 * (int64_t)r;
-        // (a streamed segment's block 0 takes the boundary path, which adds the running GHASH value)
-        if (v0 >= na && v0 + 64 <= na + nfull && !(J0DEV && d.ystate && v0 == 0)) {
-            // all 64 lanes hold whole data blocks
-            const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
-            const u32x4 x = in_g[j];
-            // counters of this row: base + lane (mod 2^32); the upper 24 bits
-            // change at most once inside a row, and then by one
-            const uint32_t base = (uint32_t)(v0 - na) + c1;
-            const uint32_t h = base >> 8;
-            if (h != hc) {
-                cur = ctr_round2(h, c, rk, te);
-                hc = h;
-            }
-            Ctr2 q = cur;
-            if ((base & 255u) > 192u) {
-                const uint32_t h1 = (h + 1u) & 0xffffffu;
-                const Ctr2 nxt = ctr_round2(h1, c, rk, te);
-                const bool up = (base & 255u) + (uint32_t)lane > 255u;
-                q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
-                cur = nxt;
-                hc = h1;
-            }
-            const u32x4 ks = aes_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
-            const u32x4 o = x ^ ks;
-            __builtin_nontemporal_store(o, out_g + j);
-            if (GH)
-                a = ghash_mul8(a, enc ? o : x, lds, gk);
-        } else {
-            boundary_row(v0);
+        const uint64_t j0 = (uint64_t)(vbase + 64 * (int64_t)r - na);  // first data block of the row (uniform)
+        const GLOBAL_AS uint8_t *src = reinterpret_cast<const GLOBAL_AS uint8_t *>(in_g + j0);
+        GLOBAL_AS uint8_t *dst = reinterpret_cast<GLOBAL_AS uint8_t *>(out_g + j0);
+        const u32x4 x = *reinterpret_cast<const GLOBAL_AS u32x4 *>(src + loff);
+        // counters of this row: base + lane (mod 2^32); the upper 24 bits
+        // change at most once inside a row, and then by one
+        const uint32_t base = (uint32_t)j0 + c1;
+        const uint32_t h = base >> 8;
+        if (h != hc) {
+            cur = ctr_round2(h, c, rk, te);
+            hc = h;
         }
+        Ctr2 q = cur;
+        if ((base & 255u) > 192u) {
+            const uint32_t h1 = (h + 1u) & 0xffffffu;
+            const Ctr2 nxt = ctr_round2(h1, c, rk, te);
+            const bool up = (base & 255u) + (uint32_t)lane > 255u;
+            q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
+            cur = nxt;
+            hc = h1;
+        }
+        const u32x4 ks = aes_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
+        const u32x4 o = x ^ ks;
+        __builtin_nontemporal_store(o, reinterpret_cast<GLOBAL_AS u32x4 *>(dst + loff));
+        if (GH)
+            a = ghash_mul8(a, enc ? o : x, lds, gk);
     }
+    for (; r < R; ++r)
+        boundary_row(vbase + 64 * (int64_t)r);
     if (!GH)
         return;
 

@@ -137,10 +137,11 @@ def test_serving_batch_that_cannot_launch_fails_closed():
     memory budget is exhausted) completes its requests with that status: the
     wait reports GCM_E_NOMEM, a decrypt is never accepted, and the stats count
     the requests as completed and failed."""
-    # budget: the context's tables, Frobenius tables and two key slots, and
-    # nothing for the serving loop's per-batch scratch
+    # budget: the context's AES tables (TE0, the S-box, TE1..TE3: 5 x 256
+    # words), Frobenius tables, two key slots and the 256-byte result block,
+    # and nothing for the serving loop's per-batch scratch
     slot_bytes = 2048 + 65536 + 40 * 8192 + 16384
-    budget = 2 * 256 * 4 + 47 * 4096 * 16 + 2 * slot_bytes + 256
+    budget = 5 * 256 * 4 + 47 * 4096 * 16 + 2 * slot_bytes + 256
     c = gcm.Context(device=0, hbm_budget=budget, key_slots=2)
     try:
         key, iv = bytes(range(16)), bytes(12)
