@@ -161,6 +161,29 @@ int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, siz
                              const uint8_t *tag_d, uint8_t *pt_d, int32_t *accept_d, void *workspace_d,
                              uint64_t workspace_bytes, void *stream);
 
+/* gcm_encrypt_async without a workspace argument, for callers that cannot
+ * allocate device memory around the call: code being captured into a HIP
+ * graph, tight serving loops, harnesses that forbid hipMalloc.  The tile
+ * partials, E_K(J0) and J0 live in a fixed device array of
+ * GCM_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on
+ * until the process ends (its address is looked up once per device, when the
+ * first context on that device is created).  The call itself performs no
+ * device or host allocation and no memset: it enqueues the same kernels as
+ * gcm_encrypt_async, with tiles enlarged (up to 2^16 blocks, results
+ * unchanged) until the partials fit.  A message whose partials still do not
+ * fit (beyond every length SP 800-38D allows combined with about 238 MiB of
+ * AAD) is GCM_E_NOMEM with nothing launched.  Every call on one device shares
+ * that device's array and every value in it is written before it is read
+ * within a call, so a call depends on nothing an earlier call left there;
+ * but two calls whose work overlaps on one device (different streams, or
+ * different contexts) race on it and may produce wrong tags: order them on
+ * one stream or synchronise between them.  Arguments, layout and the other
+ * errors are those of gcm_encrypt_async. */
+#define GCM_NOALLOC_SCRATCH_BYTES ((1ull << 20) + 4096)
+int gcm_encrypt_async_noalloc(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
+                              uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d, uint8_t *tag_d,
+                              void *stream);
+
 /* ---------------------------------------------------------------- counter mode only, GMAC */
 
 /* AES-CTR without authentication (the paper's CTR-only baseline, the "E2E CTR"

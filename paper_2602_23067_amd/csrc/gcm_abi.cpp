@@ -20,6 +20,8 @@
 
 using namespace gcm;
 
+static_assert(kNoAllocScratchBytes == GCM_NOALLOC_SCRATCH_BYTES, "scratch size and its public constant differ");
+
 // ---------------------------------------------------------------- errors
 
 // a fixed buffer: recording an error never allocates (and so never throws)
@@ -122,6 +124,11 @@ extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_byt
             e = hipHostMalloc(reinterpret_cast<void **>(&ctx->h_io), 256, hipHostMallocDefault);
             if (e != hipSuccess)
                 rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
+        }
+        if (rc == GCM_OK) {
+            e = scratch_address(device, &ctx->d_scratch);
+            if (e != hipSuccess)
+                rc = fail_hip(e, "hipGetSymbolAddress(scratch)");
         }
         if (rc == GCM_OK) {
             e = launch_init_tables(ctx->d_tables, ctx->d_tables + 256, ctx->d_frob, nullptr);
@@ -509,9 +516,16 @@ int gcm::async_launch(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *i
     MsgDesc d;
     fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)tag_d,
               (uint64_t)ok_d, (uint64_t)(ctx->d_slots + kSlotBytes * slot), ctx->slot_nr[slot], sh.log2B, sh.waves, 0);
-    if (ws_bytes < workspace_bytes_for(d.n_tiles, 1))
-        return fail(fit_ws ? GCM_E_NOMEM : GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed",
-                    (unsigned long long)ws_bytes, (unsigned long long)workspace_bytes_for(d.n_tiles, 1));
+    if (ws_bytes < workspace_bytes_for(d.n_tiles, 1)) {
+        if (fit_ws)
+            return fail(GCM_E_NOMEM,
+                        "message of %llu data and %llu AAD bytes needs %llu bytes of scratch even with tiles of "
+                        "2^%u blocks; the allocation-free path has a fixed %llu",
+                        (unsigned long long)len, (unsigned long long)aad_len,
+                        (unsigned long long)workspace_bytes_for(d.n_tiles, 1), sh.log2B, (unsigned long long)ws_bytes);
+        return fail(GCM_E_ARG, "workspace of %llu bytes is smaller than the %llu needed", (unsigned long long)ws_bytes,
+                    (unsigned long long)workspace_bytes_for(d.n_tiles, 1));
+    }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess)
         return fail_hip(e, "hipSetDevice");
@@ -546,6 +560,20 @@ extern "C" int gcm_decrypt_verify_async(gcm_ctx *ctx, uint32_t slot, const uint8
     GCM_ABI_TRY
         return async_launch(ctx, 1, slot, iv, iv_len, aad_d, aad_len, ct_d, len, pt_d, tag_d, accept_d, workspace_d,
                             workspace_bytes, false, stream);
+    GCM_ABI_CATCH
+}
+
+extern "C" int gcm_encrypt_async_noalloc(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len,
+                                         const uint8_t *aad_d, uint64_t aad_len, const uint8_t *pt_d, uint64_t len,
+                                         uint8_t *ct_d, uint8_t *tag_d, void *stream)
+{
+    GCM_ABI_TRY
+        if (!ctx)
+            return fail(GCM_E_ARG, "NULL context");
+        if (!ctx->d_scratch)
+            return fail(GCM_E_INTERNAL, "the device scratch address was not looked up");
+        return async_launch(ctx, 0, slot, iv, iv_len, aad_d, aad_len, pt_d, len, ct_d, tag_d, nullptr,
+                            ctx->d_scratch, kNoAllocScratchBytes, true, stream);
     GCM_ABI_CATCH
 }
 

@@ -30,6 +30,9 @@ struct gcm_ctx {
     uint8_t *d_ws = nullptr;
     uint64_t ws_bytes = 0;
     uint8_t *d_io = nullptr;  // device tag (16 B) + flag (4 B)
+    // the device's fixed scratch (kNoAllocScratchBytes, shared by every
+    // context on the device; its address, looked up at context creation)
+    void *d_scratch = nullptr;
     uint8_t *h_io = nullptr;  // pinned mirror
     // launch shape overrides (0 = automatic)
     uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0, cfg_fanin = 0;
@@ -162,6 +165,8 @@ int max_groups_per_cu(int waves);
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
                           uint32_t *counters, uint32_t fanin, hipStream_t s);
 hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s);
+// device address of the fixed scratch array on `device` (looked up once per device)
+hipError_t scratch_address(int device, void **out);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,
                            hipStream_t s);
 // AES-GCM-SIV: message keys into the slot at out_slot (and, with tag_in, the

@@ -88,6 +88,11 @@ struct MsgDesc {
     uint64_t yout;       // the combine writes the segment's GHASH value here instead of forming a tag
 };
 
+// Bytes of the fixed device scratch behind the allocation-free entry point:
+// with tiles of up to 2^16 blocks its 65774 tile partials cover every
+// message length SP 800-38D allows together with up to 238 MiB of AAD.
+constexpr uint64_t kNoAllocScratchBytes = (1ull << 20) + 4096;  // GCM_NOALLOC_SCRATCH_BYTES
+
 // IVs other than 96 bits: J0 = GHASH_H(IV || 0-pad || 0^64 || [len(IV)]_64),
 // computed on the device from IV bytes passed by value
 constexpr int kMaxIvBytes = 1024;

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "gcm_internal.h"
 
 namespace gcm {
@@ -1947,6 +1949,47 @@ hipError_t launch_siv_tiles(int waves, int pass, const MsgDesc &d, uint32_t n_it
     default:
         return hipErrorInvalidValue;
     }
+}
+
+// ---------------------------------------------------------------- fixed device scratch
+
+// Workspace of the allocation-free entry point: a module-scope array that
+// every device the library runs on holds until the process ends.  Host code
+// never passes its name to a kernel (on the host it is only a stand-in
+// symbol); it passes the device address looked up below.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current and kept for every later context on it.
+hipError_t scratch_address(int device, void **out)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess)
+            return e;
+        if (cur != device) {
+            e = hipSetDevice(device);
+            if (e != hipSuccess)
+                return e;
+        }
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != device)
+            (void)hipSetDevice(cur);
+        if (e != hipSuccess)
+            return e;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
 }
 
 }  // namespace gcm

@@ -26,6 +26,9 @@ GCM_E_ALIAS = -8
 GCM_E_SLOT = -9
 GCM_E_INTERNAL = -10
 
+# bytes of the fixed device scratch behind encrypt_async_noalloc (GCM_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = (1 << 20) + 4096
+
 _lib: Optional[ctypes.CDLL] = None
 
 
@@ -125,6 +128,7 @@ def load() -> ctypes.CDLL:
         "gcm_workspace_size": ([vp, u64, u64], u64),
         "gcm_encrypt_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, u64, vp], ctypes.c_int),
         "gcm_decrypt_verify_async": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp, vp, u64, vp], ctypes.c_int),
+        "gcm_encrypt_async_noalloc": ([vp, u32, vp, sz, vp, u64, vp, u64, vp, vp, vp], ctypes.c_int),
         "gcm_set_launch": ([vp, u32, u32, u32], ctypes.c_int),
         "gcm_key_register_many": ([vp, vp, vp, u32, vp, vp], ctypes.c_int),
         "gcm_batch_create": ([vp, vp, u32, vp, u64, ctypes.POINTER(vp)], ctypes.c_int),
@@ -407,6 +411,13 @@ class Context:
                                         0 if aad is None else aad.numel(), _dev(pt),
                                         0 if pt is None else pt.numel(), _dev(ct), _dev(tag_d), _dev(workspace),
                                         workspace.numel(), _stream(stream)))
+
+    def encrypt_async_noalloc(self, slot: int, iv: bytes, aad, pt, ct, tag_d, stream=None) -> None:
+        """encrypt_async with the library's fixed device scratch instead of a workspace."""
+        _check(load().gcm_encrypt_async_noalloc(self._h, slot, _host(iv), len(iv), _dev(aad),
+                                                0 if aad is None else aad.numel(), _dev(pt),
+                                                0 if pt is None else pt.numel(), _dev(ct), _dev(tag_d),
+                                                _stream(stream)))
 
     def decrypt_verify_async(self, slot: int, iv: bytes, aad, ct, tag_d, pt, accept_d, workspace,
                              stream=None) -> None:

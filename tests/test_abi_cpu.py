@@ -98,3 +98,13 @@ def test_header_is_plain_c(tmp_path):
     subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-fsyntax-only",
                     "-I", inc, str(prog)], check=True)
     subprocess.run(["g++", "-std=c++11", "-Wall", "-Werror", "-fsyntax-only", "-x", "c++", hdr], check=True)
+
+
+def test_noalloc_scratch_size_matches_the_header():
+    """The binding's constant for the fixed device scratch is the header's."""
+    from paper_2602_23067_amd import gcm
+
+    text = open(os.path.join(ROOT, "include", "gcm_mi355.h")).read()
+    m = re.search(r"#define GCM_NOALLOC_SCRATCH_BYTES \(\(1ull << (\d+)\) \+ (\d+)\)", text)
+    assert m, "GCM_NOALLOC_SCRATCH_BYTES not found"
+    assert gcm.NOALLOC_SCRATCH_BYTES == (1 << int(m.group(1))) + int(m.group(2))
