@@ -241,11 +241,11 @@ int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes);
 /* ---------------------------------------------------------------- streamed messages */
 
 /* One message fed in segments (inputs larger than HBM, or arriving over
- * time): the (GHASH value, block count) pair of SP 800-38D's GHASH is carried
- * across calls on the device, with the same tiles, counters and combine as a
- * single call, so the ciphertext and tag equal gcm_encrypt's on the
- * concatenated input (the paper's map-reduce across segments, "Scalable
- * MapReduce for Massive Files").  All calls of one stream object are enqueued
+ * time): each segment's tile partials stay on the device, and the final call
+ * reduces them all, each segment's GHASH value multiplied by H^(blocks after
+ * it) (GHASH is linear in its input), so the ciphertext and tag equal
+ * gcm_encrypt's on the concatenated input (the paper's map-reduce across
+ * segments, "Scalable MapReduce for Massive Files").  All calls of one stream object are enqueued
  * on the given HIP stream in call order without host synchronisation; give
  * them one stream (or order them).  Key: a registered slot.  IV: 1..1024
  * bytes.  Decrypt-verify releases plaintext segment by segment; the caller
@@ -253,7 +253,8 @@ int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes);
 typedef struct gcm_stream gcm_stream;
 
 /* op 0 encrypt / 1 decrypt-verify; the AAD (device, 16-byte aligned, may be
- * empty) is hashed here.  Allocates the stream's device state from the
+ * empty) is hashed here.  Allocates the stream's partials buffer (4 MiB,
+ * doubled when full, 16 bytes per wave tile of every segment) from the
  * context budget. */
 int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
                      const uint8_t *aad_d, uint64_t aad_len, gcm_stream **out, void *stream);

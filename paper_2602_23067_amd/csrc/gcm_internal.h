@@ -83,8 +83,8 @@ struct MsgDesc {
     uint32_t pad0;
     uint64_t j0;         // device address of J0 (16 bytes) for IVs other than 96 bits; 0: J0 = IV || 0^31 || 1
     uint32_t tag_len;    // tag bytes written (encrypt) or compared (decrypt): 16, or 15, 14, 13, 12, 8, 4
-    uint32_t ctr_off;    // with j0: data blocks that precede this one (a streamed segment), added to the counters
-    uint64_t ystate;     // with j0: GHASH value of the blocks before this segment, XORed into its block 0
+    uint32_t ctr_off;    // a streamed segment: data blocks that precede it, added to the counters
+    uint64_t lift;       // with yout: the combine multiplies the segment's GHASH value by H^lift (< 2^40)
     uint64_t yout;       // the combine writes the segment's GHASH value here instead of forming a tag
 };
 

@@ -923,14 +923,12 @@ __device__ __forceinline__ u32x4 gf_mul_lanewin(u32x4 a, const uint8_t *__restri
 // p_t = sum_l a_l * H^(63-l) is formed by exponent-bit fix-ups and an XOR
 // across the wave.  With GH false the tile is counter mode only (no GHASH,
 // no partial).  AADROWS adds a GHASH-only pass over rows of whole AAD blocks,
-// J0DEV reads J0 from device memory (IVs other than 96 bits, streamed
-// segments) instead of forming IV || 0^31 || 1, offsets the counters by
-// d.ctr_off, and continues a streamed GHASH: the running value *d.ystate is
-// XORed into block 0 of the segment, since Horner from state Y over X_1..X_m
-// equals Horner from zero over (X_1 ^ Y), X_2, ..., X_m.  Both options cost
-// the main loop its batching of LDS reads
-// (a run-time counter base, or the extra loop, leaves it fewer registers), so
-// each is compiled only into kernel variants of its own.
+// J0DEV reads J0 from device memory (IVs other than 96 bits) instead of
+// forming IV || 0^31 || 1.  A streamed segment's counters start d.ctr_off
+// blocks after J0 + 1 in every variant.  Both options cost the main loop its
+// batching of LDS reads (a run-time counter base, or the extra loop, leaves
+// it fewer registers), so each is compiled only into kernel variants of its
+// own.
 template <int NR, bool GH, bool AADROWS, bool J0DEV>
 __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restrict__ lds, const LaneK &lk,
                           const GhK &gk, const uint32_t *__restrict__ te0g, u32x4 *__restrict__ partials)
@@ -940,15 +938,17 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     const CONST_AS uint32_t *rk_base = cptr<uint32_t>(reinterpret_cast<const void *>(d.slot));
     const CONST_AS uint32_t *rk = rk_base;
     // J0 = IV || 0^31 || 1, or a J0 computed from a longer or shorter IV;
-    // data block j uses counter value c1 + j, E_K(J0) counter value c1 - 1
-    uint32_t iv0 = d.iv[0], iv1 = d.iv[1], iv2 = d.iv[2], c1 = 2u;
+    // E_K(J0) uses J0's own counter value cj0, data block j (of a streamed
+    // segment that follows d.ctr_off earlier blocks) counter value c1 + j
+    uint32_t iv0 = d.iv[0], iv1 = d.iv[1], iv2 = d.iv[2], cj0 = 1u;
     if (J0DEV) {
         const CONST_AS uint32_t *jw = cptr<uint32_t>(reinterpret_cast<const void *>(d.j0));
         iv0 = jw[0];
         iv1 = jw[1];
         iv2 = jw[2];
-        c1 = bswap32(jw[3]) + 1u + d.ctr_off;
+        cj0 = bswap32(jw[3]);
     }
+    const uint32_t c1 = cj0 + 1u + d.ctr_off;
     AesCtx c;
     {
         const uint32_t s0 = iv0 ^ rk[0], s1 = iv1 ^ rk[1], s2 = iv2 ^ rk[2];
@@ -962,7 +962,7 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     if (GH && t == 0) {
         // E_K(J0) is the keystream block of counter value 1; the wave that owns
         // tile 0 leaves it after the message's partials for the combine
-        const u32x4 ek = aes_ctr<NR>(c1 - 1u, c, rk, lds, lk);
+        const u32x4 ek = aes_ctr<NR>(cj0, c, rk, lds, lk);
         if (lane == 0)
             partials[d.tile_base + d.n_tiles] = ek;
     }
@@ -1001,8 +1001,6 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             X = u32x4{bswap32((uint32_t)(abits >> 32)), bswap32((uint32_t)abits), bswap32((uint32_t)(cbits >> 32)),
                       bswap32((uint32_t)cbits)};
         }
-        if (GH && J0DEV && d.ystate && v == 0)
-            X ^= load_const<u32x4>(reinterpret_cast<const void *>(d.ystate));
         if (GH)
             a = ghash_mul8(a, X, lds, gk);
     };
@@ -1026,19 +1024,16 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
         }
     }
 
-    // Rows [fa, fb) hold 64 whole data blocks each and take the fast path:
-    // v0 >= na and v0 + 64 <= na + nfull, except a streamed segment's block 0
-    // (v0 == 0), which takes the boundary path that adds the running GHASH
-    // value.  The range is computed once, so the row loop keeps only scalar
-    // 32-bit bookkeeping and one uniform row address.
+    // Rows [fa, fb) hold 64 whole data blocks each and take the fast path
+    // (v0 >= na and v0 + 64 <= na + nfull).  The range is computed once, so
+    // the row loop keeps only scalar 32-bit bookkeeping and one uniform row
+    // address.
     int64_t rf0, rf1;
     {
         const int64_t lo = na - vbase;                // 64 r >= lo
         const int64_t hi = na + nfull - vbase - 64;   // 64 r <= hi
         rf0 = lo <= 0 ? 0 : (lo + 63) >> 6;
         rf1 = hi < 0 ? 0 : (hi >> 6) + 1;
-        if (J0DEV && d.ystate && rf0 < rf1 && vbase + 64 * rf0 == 0)
-            ++rf0;
     }
     const uint32_t fa = (uint32_t)(rf0 > (int64_t)r ? (rf0 < (int64_t)R ? rf0 : (int64_t)R) : (int64_t)r);
     const uint32_t fb = (uint32_t)(rf1 > (int64_t)fa ? (rf1 < (int64_t)R ? rf1 : (int64_t)R) : (int64_t)fa);
@@ -1336,11 +1331,23 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
     }
     // * H, by the first half-wave
     const u32x4 s = mul_tab4_half(i < 32 ? leaf[0] : u32x4{0, 0, 0, 0}, tabs[0], i & 31u, i < 32);
-    if (i == 0) {
-        if (d.yout) {  // a streamed segment: hand on its GHASH value
-            *reinterpret_cast<u32x4 *>(d.yout) = s;
+    if (d.yout) {
+        // a streamed segment (or a POLYVAL pass): hand on its GHASH value,
+        // first multiplied by H^lift (the blocks of the message that follow
+        // the segment) with the key slot's nibble tables of H^(2^k), one
+        // half-wave product per set bit
+        if (i >= 64)
             return;
-        }
+        u32x4 y = s;
+        const u32x4 *g4 = reinterpret_cast<const u32x4 *>(d.slot + kSlotTab4Off);
+        for (uint64_t e = d.lift, k = 0; e && k < (uint64_t)kTab4Levels; e >>= 1, ++k)
+            if (e & 1u)
+                y = mul_tab4_half(y, g4 + k * 512, i & 31u, i < 32);
+        if (i == 0)
+            *reinterpret_cast<u32x4 *>(d.yout) = y;
+        return;
+    }
+    if (i == 0) {
         const u32x4 tag = s ^ partials[d.tile_base + T];
         const uint32_t tw[4] = {tag.x, tag.y, tag.z, tag.w};
         const int tl = (int)d.tag_len;  // T = MSB_t of the full tag
@@ -1360,6 +1367,37 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
                 counters[1 + pos] = BATCH ? blockIdx.x : 0u;
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------- streamed message tag
+
+// GHASH of a message fed in segments is the XOR of the segments' own GHASH
+// values, each multiplied by H^(blocks after it) (the combine's lift); the
+// tag adds E_K(J0).  One wave: lane l XORs values l, l + 64, ..., then an
+// XOR across the wave.  Encrypt writes tag_len bytes of the tag; decrypt
+// compares them without early exit and writes the accept flag.
+__global__ __launch_bounds__(64) void k_gcm_fold(const u32x4 *__restrict__ vals, uint32_t k,
+                                                 const u32x4 *__restrict__ ekj0, uint8_t *tag, int32_t *ok,
+                                                 uint32_t op, uint32_t tag_len)
+{
+    const uint32_t lane = threadIdx.x;
+    u32x4 acc = {0, 0, 0, 0};
+    for (uint32_t j = lane; j < k; j += 64)
+        acc ^= vals[j];
+    acc = wave_xor_reduce(acc);
+    if (lane != 0)
+        return;
+    const u32x4 t = acc ^ *ekj0;
+    const uint32_t tw[4] = {t.x, t.y, t.z, t.w};
+    if (op == 0) {
+        for (uint32_t b = 0; b < tag_len; ++b)
+            tag[b] = (uint8_t)(tw[b >> 2] >> (8 * (b & 3)));
+    } else {
+        uint32_t diff = 0;
+        for (uint32_t b = 0; b < tag_len; ++b)
+            diff |= ((tw[b >> 2] >> (8 * (b & 3))) & 0xffu) ^ tag[b];
+        *ok = diff == 0 ? 1 : 0;
     }
 }
 
@@ -1869,6 +1907,14 @@ hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *
     default:
         return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const void *vals, uint32_t k, const void *ekj0, uint8_t *tag, int32_t *ok, uint32_t op,
+                       uint32_t tag_len, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gcm_fold, dim3(1), dim3(64), 0, s, reinterpret_cast<const u32x4 *>(vals), k,
+                       reinterpret_cast<const u32x4 *>(ekj0), tag, ok, op, tag_len);
     return hipGetLastError();
 }
 

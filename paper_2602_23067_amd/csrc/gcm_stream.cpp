@@ -1,20 +1,22 @@
 // gcm_stream.cpp -- streamed AES-GCM: one message fed as a sequence of
-// device-resident segments, with (GHASH value, block count) carried across
-// calls on the device (the monoid combine(L, R) = L*H^|R| ^ R, applied here
-// as a Horner continuation).
+// device-resident segments (the paper's map-reduce across pieces of a
+// message too large to hold at once).
 //
-// Each segment is an ordinary tile launch of the device-J0 kernel variant:
-// its counters start at J0 + 1 + (blocks before it), the running GHASH value
-// Y is XORed into its first block (Horner from Y over X_1..X_m equals Horner
-// from zero over X_1 ^ Y, X_2, ..., X_m), and the combine writes the result
-// back as the new Y.  The AAD is the first segment; the final call is a
-// segment made of the length block alone, whose combine adds E_K(J0) and
-// writes (or checks) the tag.
+// GHASH is linear in its input, so the GHASH of X = X_1 || X_2 || ... || X_K
+// is the XOR over segments of GHASH(X_k) * H^(blocks after X_k).  Each update
+// therefore runs only the tile kernel over its segment (its counters start
+// after the blocks fed so far) and leaves the segment's tile partials in the
+// stream's partials buffer; nothing depends on the previous segment.  The
+// final call adds the length block as one more segment, reduces every
+// segment's partials in one batched combine launch (each segment's value
+// lifted by H^(blocks after it)), and one small kernel XORs the lifted values
+// with E_K(J0) into the tag or the accept flag.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/gcm_mi355.h"
 #include "gcm_host.h"
@@ -30,64 +32,86 @@ struct gcm_stream {
     uint64_t len = 0;      // payload bytes fed so far
     bool tail = false;     // a segment that was not a whole number of blocks has been fed
     bool closed = false;   // final was called
-    uint8_t *d_state = nullptr;  // 16 B running GHASH value, then 16 B J0
-    void *ws = nullptr;
-    uint64_t ws_bytes = 0;
+    uint8_t iv[12] = {0};  // a 96-bit IV (j0 == nullptr)
+    uint8_t *d_j0 = nullptr;  // J0 for other IV lengths (16 B)
+    // counter block + reject list (256 B), then per segment its tile partials
+    // and the slot where its tile-0 wave leaves E_K(J0)
+    uint8_t *d_part = nullptr;
+    uint64_t part_bytes = 0;  // allocated
+    uint64_t part_slots = 0;  // 16-byte slots in use after the header
+    std::vector<MsgDesc> segs;
+    uint32_t fanin = 2;
 };
 
-static constexpr uint64_t kStateBytes = 256;
+static constexpr uint64_t kHeader = 256;  // workspace_counter_bytes(1)
+static constexpr uint64_t kJ0Bytes = 256;
 
-static int stream_ws(gcm_stream *st, uint64_t bytes)
+// room for `slots` more 16-byte slots (and `extra` bytes after them); a
+// larger buffer takes over the slots written so far (stream-ordered copy)
+static int part_reserve(gcm_stream *st, uint64_t slots, uint64_t extra, hipStream_t s)
 {
-    if (st->ws_bytes >= bytes)
+    const uint64_t need = kHeader + 16 * (st->part_slots + slots) + extra;
+    if (need <= st->part_bytes)
         return GCM_OK;
-    ctx_free(st->ctx, st->ws, st->ws_bytes);
-    st->ws = nullptr;
-    st->ws_bytes = 0;
-    const uint64_t want = std::max<uint64_t>(bytes, 1ull << 16);
-    int rc = ctx_alloc(st->ctx, &st->ws, want);
+    const uint64_t want = std::max<uint64_t>(need, std::max<uint64_t>(2 * st->part_bytes, 4ull << 20));
+    uint8_t *p = nullptr;
+    int rc = ctx_alloc(st->ctx, reinterpret_cast<void **>(&p), want);
     if (rc)
         return rc;
-    st->ws_bytes = want;
+    if (st->part_slots) {
+        hipError_t e = hipMemcpyAsync(p, st->d_part, kHeader + 16 * st->part_slots, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);  // the old buffer is freed below
+        if (e != hipSuccess) {
+            ctx_free(st->ctx, p, want);
+            return fail_hip(e, "stream partials copy");
+        }
+    }
+    ctx_free(st->ctx, st->d_part, st->part_bytes);
+    st->d_part = p;
+    st->part_bytes = want;
     return GCM_OK;
 }
 
-// one segment: n_aad AAD blocks or data blocks (never both), or the length
-// block alone (final); geometry over exactly its own blocks
-static int run_segment(gcm_stream *st, const MsgDesc &base, hipStream_t s)
+// A segment of d.m GHASH blocks (AAD blocks, data blocks, or the length block
+// alone): tile launch with the single-message shape for that size; its
+// partials and E_K(J0) slot go to the next free slots of the buffer.
+static int run_segment(gcm_stream *st, MsgDesc d, hipStream_t s)
 {
     gcm_ctx *ctx = st->ctx;
-    MsgDesc d = base;
-    // the single-message shape for a message of this segment's blocks
     const Shape sh = message_shape(ctx, (st->nr - 6) * 4, d.m * 16, 0);
-    const uint32_t log2B = sh.log2B, waves = sh.waves;
-    const uint64_t B = 1ull << log2B;
-    d.log2B = log2B;
+    const uint64_t B = 1ull << sh.log2B;
+    d.log2B = sh.log2B;
     d.n_tiles = (d.m + B - 1) / B;
     d.z = d.n_tiles * B - d.m;
     d.tile_lo = 0;
     d.tile_hi = d.n_tiles;
-    d.groups = (uint32_t)((d.n_tiles + waves - 1) / waves);
-    int rc = stream_ws(st, workspace_bytes_for(d.n_tiles, 1));
+    d.groups = (uint32_t)((d.n_tiles + sh.waves - 1) / sh.waves);
+    int rc = part_reserve(st, d.n_tiles + 1, 0, s);
     if (rc)
         return rc;
-    rc = launch_tile_range(ctx, d, sh, st->ws, s);
+    d.tile_base = st->part_slots;
+    rc = launch_tile_range(ctx, d, sh, st->d_part, s);
     if (rc)
         return rc;
-    uint32_t *counters = reinterpret_cast<uint32_t *>(st->ws);
-    const uint8_t *partials = reinterpret_cast<const uint8_t *>(st->ws) + workspace_counter_bytes(1);
-    hipError_t e = launch_combine(nullptr, 1, &d, partials, counters, sh.fanin, s);
-    if (e != hipSuccess)
-        return fail_hip(e, "combine launch");
+    st->part_slots += d.n_tiles + 1;
+    st->fanin = sh.fanin;
+    st->segs.push_back(d);
     return GCM_OK;
 }
 
 static void segment_desc(const gcm_stream *st, MsgDesc *d)
 {
-    static const uint8_t zero_iv[12] = {0};
-    fill_desc(d, st->op, zero_iv, 0, 0, 0, 0, 0, 0, 0, (uint64_t)(st->ctx->d_slots + kSlotBytes * st->slot), st->nr,
-              6, 16, 0);
-    d->j0 = (uint64_t)(st->d_state + 16);
+    fill_desc(d, st->op, st->iv, 0, 0, 0, 0, 0, 0, 0, (uint64_t)(st->ctx->d_slots + kSlotBytes * st->slot), st->nr, 6,
+              16, 0);
+    d->j0 = (uint64_t)st->d_j0;
+}
+
+static void stream_free(gcm_stream *st)
+{
+    ctx_free(st->ctx, st->d_part, st->part_bytes);
+    ctx_free(st->ctx, st->d_j0, kJ0Bytes);
+    delete st;
 }
 
 extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
@@ -119,21 +143,23 @@ extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const 
         st->slot = slot;
         st->nr = ctx->slot_nr[slot];
         st->aad_len = aad_len;
-        rc = ctx_alloc(ctx, reinterpret_cast<void **>(&st->d_state), kStateBytes);
-        if (rc) {
-            delete st;
-            return rc;
+        if (iv_len == 12) {
+            std::memcpy(st->iv, iv, 12);
+        } else {
+            // J0 = GHASH_H(IV || 0-pad || [len(IV)]_64) on the device
+            rc = ctx_alloc(ctx, reinterpret_cast<void **>(&st->d_j0), kJ0Bytes);
+            if (rc == GCM_OK) {
+                IvArg a;
+                std::memset(&a, 0, sizeof a);
+                a.len = (uint32_t)iv_len;
+                std::memcpy(a.b, iv, iv_len);
+                e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_j0, nullptr, s);
+                if (e != hipSuccess)
+                    rc = fail_hip(e, "J0 kernel launch");
+            }
         }
-        // J0 (any IV length) and Y = 0
-        IvArg a;
-        std::memset(&a, 0, sizeof a);
-        a.len = (uint32_t)iv_len;
-        std::memcpy(a.b, iv, iv_len);
-        e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_state + 16, st->d_state, s);
-        if (e != hipSuccess)
-            rc = fail_hip(e, "J0 kernel launch");
         if (rc == GCM_OK && aad_len) {
-            // segment 0: the AAD blocks, from Y = 0
+            // segment 0: the AAD blocks
             MsgDesc d;
             segment_desc(st, &d);
             d.aad = (uint64_t)aad_d;
@@ -141,14 +167,11 @@ extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const 
             d.na = (aad_len + 15) / 16;
             d.n = 0;
             d.m = d.na;
-            d.yout = (uint64_t)st->d_state;
             rc = run_segment(st, d, s);
         }
         if (rc) {
             (void)hipStreamSynchronize(s);
-            ctx_free(ctx, st->ws, st->ws_bytes);
-            ctx_free(ctx, st->d_state, kStateBytes);
-            delete st;
+            stream_free(st);
             return rc;
         }
         *out = st;
@@ -187,8 +210,6 @@ extern "C" int gcm_stream_update(gcm_stream *st, const uint8_t *in_d, uint64_t l
         d.n = (len + 15) / 16;
         d.m = d.n;
         d.ctr_off = (uint32_t)(st->len / 16);  // counters continue mod 2^32
-        d.ystate = (uint64_t)st->d_state;
-        d.yout = (uint64_t)st->d_state;
         rc = run_segment(st, d, s);
         if (rc)
             return rc;
@@ -211,7 +232,8 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         hipError_t e = hipSetDevice(ctx->device);
         if (e != hipSuccess)
             return fail_hip(e, "hipSetDevice");
-        // the length block alone: S = (Y ^ [8|A|]_64 || [8|C|]_64) * H, tag = S ^ E_K(J0)
+        // the last segment: the length block [8|A|]_64 || [8|C|]_64 alone; its
+        // tile-0 wave also leaves E_K(J0)
         MsgDesc d;
         segment_desc(st, &d);
         d.aad_len = st->aad_len;
@@ -219,12 +241,36 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         d.na = 0;
         d.n = 0;
         d.m = 1;
-        d.ystate = (uint64_t)st->d_state;
-        d.tag = (uint64_t)tag_d;
-        d.ok = (uint64_t)accept_d;
         int rc = run_segment(st, d, s);
         if (rc)
             return rc;
+        const uint32_t k = (uint32_t)st->segs.size();
+        const uint64_t desc_bytes = (uint64_t)k * sizeof(MsgDesc);
+        rc = part_reserve(st, k, desc_bytes + 16, s);
+        if (rc)
+            return rc;
+        uint8_t *vals = st->d_part + kHeader + 16 * st->part_slots;
+        MsgDesc *d_descs = reinterpret_cast<MsgDesc *>(vals + 16 * (uint64_t)k);
+        // segment j's value is lifted by H^(GHASH blocks after it)
+        uint64_t after = 0;
+        for (uint32_t j = k; j-- > 0;) {
+            st->segs[j].yout = (uint64_t)(vals + 16 * (uint64_t)j);
+            st->segs[j].lift = after;
+            after += st->segs[j].m;
+        }
+        if (after >= (1ull << kTab4Levels))
+            return fail(GCM_E_TOOLONG, "streamed message of %llu GHASH blocks is beyond the lift tables",
+                        (unsigned long long)after);
+        e = hipMemcpyAsync(d_descs, st->segs.data(), desc_bytes, hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = launch_combine(d_descs, k, nullptr, st->d_part + kHeader, reinterpret_cast<uint32_t *>(st->d_part),
+                               st->fanin, s);
+        const MsgDesc &last = st->segs.back();
+        if (e == hipSuccess)
+            e = launch_fold(vals, k, st->d_part + kHeader + 16 * (last.tile_base + last.n_tiles), tag_d, accept_d,
+                            st->op, 16, s);
+        if (e != hipSuccess)
+            return fail_hip(e, "stream final kernels");
         st->closed = true;
         return GCM_OK;
     GCM_ABI_CATCH
@@ -238,10 +284,8 @@ extern "C" int gcm_stream_destroy(gcm_stream *st)
         gcm_ctx *ctx = st->ctx;
         std::lock_guard<std::mutex> g(ctx->mu);
         (void)hipSetDevice(ctx->device);
-        (void)hipDeviceSynchronize();  // the stream's queued segments may still read its state
-        ctx_free(ctx, st->ws, st->ws_bytes);
-        ctx_free(ctx, st->d_state, kStateBytes);
-        delete st;
+        (void)hipDeviceSynchronize();  // the stream's queued kernels may still use its buffers
+        stream_free(st);
         return GCM_OK;
     GCM_ABI_CATCH
 }
