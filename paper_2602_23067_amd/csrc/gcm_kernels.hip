@@ -1710,17 +1710,40 @@ __device__ void wave_tile_siv(const MsgDesc &d, uint64_t t, const uint8_t *__res
             a = ghash_mul8(a, rev_block(X), lds, gk);
     };
 
+    // rows [fa, fb) hold 64 whole data blocks (as in wave_tile), with the
+    // same falling issue priority over them
+    int64_t rf0, rf1;
+    {
+        const int64_t lo = na - vbase, hi = na + nfull - vbase - 64;
+        rf0 = lo <= 0 ? 0 : (lo + 63) >> 6;
+        rf1 = hi < 0 ? 0 : (hi >> 6) + 1;
+    }
+    const uint32_t fa = (uint32_t)(rf0 > (int64_t)r0 ? (rf0 < (int64_t)R ? rf0 : (int64_t)R) : (int64_t)r0);
+    const uint32_t fb = (uint32_t)(rf1 > (int64_t)fa ? (rf1 < (int64_t)R ? rf1 : (int64_t)R) : (int64_t)fa);
+    uint32_t r = r0;
+    for (; r < fa; ++r)
+        boundary_row(vbase + 64 * (int64_t)r);
     uint32_t hc = 0xffffffffu;
     Ctr2 cur = {0, 0, 0, 0};
-    for (uint32_t r = r0; r < R; ++r) {
+    const uint32_t loff = 16u * (uint32_t)lane;
+    const uint32_t span = fb - r;
+    const uint32_t q1 = r + span / 4, q2 = r + span / 2, q3 = r + 3 * (span / 4);
+    __builtin_amdgcn_s_setprio(3);
+    for (; r < fb; ++r) {
+        if (r == q1)
+            __builtin_amdgcn_s_setprio(2);
+        if (r == q2)
+            __builtin_amdgcn_s_setprio(1);
+        if (r == q3)
+            __builtin_amdgcn_s_setprio(0);
         rk = rk_base;
         asm volatile("" : "+s"(rk));
-        const int64_t v0 = vbase + 64 * (int64_t)r;
-        if (v0 >= na && v0 + 64 <= na + nfull) {
-            const uint64_t j = (uint64_t)(v0 - na) + (uint64_t)lane;
-            const u32x4 x = in_g[j];
+        const uint64_t j0 = (uint64_t)(vbase + 64 * (int64_t)r - na);  // first data block of the row (uniform)
+        {
+            const u32x4 x = *reinterpret_cast<const GLOBAL_AS u32x4 *>(
+                reinterpret_cast<const GLOBAL_AS uint8_t *>(in_g + j0) + loff);
             if (AES) {
-                const uint32_t base = (uint32_t)(v0 - na) + c0;
+                const uint32_t base = (uint32_t)j0 + c0;
                 const uint32_t h = base >> 8;
                 if (h != hc) {
                     cur = siv_round2(h, c, rk, te);
@@ -1736,16 +1759,17 @@ __device__ void wave_tile_siv(const MsgDesc &d, uint64_t t, const uint8_t *__res
                     hc = h1;
                 }
                 const u32x4 o = x ^ aes_siv_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
-                __builtin_nontemporal_store(o, out_g + j);
+                __builtin_nontemporal_store(
+                    o, reinterpret_cast<GLOBAL_AS u32x4 *>(reinterpret_cast<GLOBAL_AS uint8_t *>(out_g + j0) + loff));
                 if (GH)
                     a = ghash_mul8(a, rev_block(o), lds, gk);
             } else {
                 a = ghash_mul8(a, rev_block(x), lds, gk);
             }
-        } else {
-            boundary_row(v0);
         }
     }
+    for (; r < R; ++r)
+        boundary_row(vbase + 64 * (int64_t)r);
     if (!GH)
         return;
     a = gf_mul_lanewin(a, lds, lane);
