@@ -357,18 +357,26 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
             self.retire = retire
             self.last_lap = []  # request indices allocated since the last wrap
 
-        def take(self, i, nbytes):
-            need = (nbytes + 255) // 256 * 256
-            if self.head + need > arena.numel():
-                self.head = 0
-                self.last_lap = []
-            lo, hi = self.head, self.head + need
+        def plan(self, sizes_):
+            """Output regions of a request stream, in submission order (the
+            addresses do not depend on when requests complete)."""
+            regions, head = [], 0
+            self.last_lap = []
+            for i, nbytes in enumerate(sizes_):
+                need = (int(nbytes) + 255) // 256 * 256
+                if head + need > arena.numel():
+                    head = 0
+                    self.last_lap = []
+                regions.append((head, head + need))
+                self.last_lap.append(i)
+                head += need
+            return regions
+
+        def admit(self, i, lo, hi):
+            """Wait for the earlier requests whose regions overlap [lo, hi)."""
             while self.live and self.live[0][0] < hi and lo < self.live[0][1]:
                 self.retire(self.live.popleft()[2])
             self.live.append((lo, hi, i))
-            self.last_lap.append(i)
-            self.head = hi
-            return arena[lo:lo + nbytes]
 
     def check(pick, ops, outs, done_idx, accepted):
         """Every tag and accept flag; the outputs still intact in the arena."""
@@ -396,6 +404,14 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
             accepted[i] = int(acc)
 
         ar = Arena(retire)
+        regions = ar.plan([docs[k]["pt"].numel() for k in pick])
+        reqs = []
+        for i in range(n):  # request records built ahead, so the loop below is not Python-bound
+            x = docs[pick[i]]
+            outs[i] = arena[regions[i][0]:regions[i][0] + x["pt"].numel()]
+            reqs.append(gcm.Server.prepare(int(ops[i]), slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"],
+                                           x["pt"] if ops[i] == 0 else x["ct"], outs[i],
+                                           tags[i] if ops[i] == 0 else x["tag"]))
         tags[:n].zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -404,12 +420,8 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
             due += gaps[i]
             while time.perf_counter() < due:
                 pass
-            x = docs[pick[i]]
-            outs[i] = ar.take(i, x["pt"].numel())
-            if ops[i] == 0:
-                ids[i] = srv.submit(0, slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["pt"], outs[i], tags[i])
-            else:
-                ids[i] = srv.submit(1, slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["ct"], outs[i], x["tag"])
+            ar.admit(i, *regions[i])
+            ids[i] = srv.submit_prepared(reqs[i])
         t_sub = time.perf_counter() - t0
         while ar.live:
             retire(ar.live.popleft()[2])
@@ -469,6 +481,26 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
             evs[i].synchronize()
 
         ar = Arena(retire)
+        regions = ar.plan([docs[k]["pt"].numel() for k in pick])
+        lib = gcm.load()
+        sh = int(stream.cuda_stream)
+        calls = []
+        for i in range(n):  # argument lists built ahead, as for the served path
+            x = docs[pick[i]]
+            outs[i] = arena[regions[i][0]:regions[i][0] + x["pt"].numel()]
+            iv = gcm._host(doc_iv[pick[i]])
+            if ops[i] == 0:
+                calls.append((lib.gcm_encrypt_async, (ctx.handle, slots[doc_key[pick[i]]], iv, 12,
+                                                      x["aad"].data_ptr(), 2880, x["pt"].data_ptr(),
+                                                      x["pt"].numel(), outs[i].data_ptr(), tags[i].data_ptr(),
+                                                      ws.data_ptr(), ws.numel(), sh)))
+            else:
+                calls.append((lib.gcm_decrypt_verify_async, (ctx.handle, slots[doc_key[pick[i]]], iv, 12,
+                                                             x["aad"].data_ptr(), 2880, x["ct"].data_ptr(),
+                                                             x["ct"].numel(), x["tag"].data_ptr(),
+                                                             outs[i].data_ptr(), accept_d[i:i + 1].data_ptr(),
+                                                             ws.data_ptr(), ws.numel(), sh)))
+        evs_pool = [torch.cuda.Event() for _ in range(n)]
         tags[:n].zero_()
         accept_d[:n].fill_(-1)
         torch.cuda.synchronize()
@@ -480,15 +512,11 @@ def run_serving_config5(ctx, gcm, workloads, torch, n_docs, n_reqs, loads=(0.5, 
             while time.perf_counter() < due:
                 pass
             arrive[i] = max(due, time.perf_counter()) if qps else t0
-            x = docs[pick[i]]
-            outs[i] = ar.take(i, x["pt"].numel())
-            if ops[i] == 0:
-                ctx.encrypt_async(slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["pt"], outs[i], tags[i], ws,
-                                  stream)
-            else:
-                ctx.decrypt_verify_async(slots[doc_key[pick[i]]], doc_iv[pick[i]], x["aad"], x["ct"], x["tag"],
-                                         outs[i], accept_d[i:i + 1], ws, stream)
-            ev = torch.cuda.Event()
+            ar.admit(i, *regions[i])
+            fn, a = calls[i]
+            if fn(*a) != 0:
+                raise RuntimeError(lib.gcm_last_error().decode())
+            ev = evs_pool[i]
             ev.record(stream)
             evs[i] = ev
             with cv:

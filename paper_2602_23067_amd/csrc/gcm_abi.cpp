@@ -126,6 +126,20 @@ extern "C" int gcm_ctx_create(gcm_ctx **out, int device, uint64_t hbm_budget_byt
                 rc = fail(GCM_E_NOMEM, "hipHostMalloc: %s", hipGetErrorString(e));
         }
         if (rc == GCM_OK) {
+            // optional: without a mapped result block the one-shot calls copy
+            if (hipHostMalloc(reinterpret_cast<void **>(&ctx->h_map), 256,
+                              hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+                if (hipHostGetDevicePointer(reinterpret_cast<void **>(&ctx->d_map), ctx->h_map, 0) != hipSuccess) {
+                    (void)hipHostFree(ctx->h_map);
+                    ctx->h_map = nullptr;
+                    ctx->d_map = nullptr;
+                }
+            } else {
+                ctx->h_map = nullptr;
+            }
+            (void)hipGetLastError();
+        }
+        if (rc == GCM_OK) {
             e = scratch_address(device, &ctx->d_scratch);
             if (e != hipSuccess)
                 rc = fail_hip(e, "hipGetSymbolAddress(scratch)");
@@ -172,6 +186,8 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
         }
         if (ctx->h_io)
             (void)hipHostFree(ctx->h_io);
+        if (ctx->h_map)
+            (void)hipHostFree(ctx->h_map);
         delete ctx;
         return GCM_OK;
     GCM_ABI_CATCH
@@ -611,12 +627,20 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     rc = cached_slot_locked(ctx, key, key_len, &slot, s);
     if (rc)
         return rc;
-    uint8_t *d_tag = ctx->d_io;                                 // 16 bytes
-    int32_t *d_ok = reinterpret_cast<int32_t *>(ctx->d_io + 16);  // 4 bytes
+    // the tag (16 bytes) and the accept flag (4 bytes): in the mapped result
+    // block, which the combine reads and writes directly, else on the device
+    // with copies
+    const bool mapped = ctx->d_map != nullptr;
+    uint8_t *d_tag = mapped ? ctx->d_map : ctx->d_io;
+    int32_t *d_ok = reinterpret_cast<int32_t *>(d_tag + 16);
     if (op == 1) {
-        e = hipMemcpyAsync(d_tag, tag_in, tag_len, hipMemcpyHostToDevice, s);
-        if (e != hipSuccess)
-            return fail_hip(e, "tag upload");
+        if (mapped) {
+            std::memcpy(ctx->h_map, tag_in, tag_len);
+        } else {
+            e = hipMemcpyAsync(d_tag, tag_in, tag_len, hipMemcpyHostToDevice, s);
+            if (e != hipSuccess)
+                return fail_hip(e, "tag upload");
+        }
     }
     MsgDesc d;
     fill_desc(&d, op, kZeroIv, (uint64_t)aad_d, aad_len, (uint64_t)in_d, (uint64_t)out_d, len, (uint64_t)d_tag,
@@ -628,16 +652,17 @@ static int oneshot(gcm_ctx *ctx, uint32_t op, const uint8_t *key, size_t key_len
     rc = launch_single(ctx, d, sh, ctx->d_ws, s);
     if (rc)
         return rc;
-    e = hipMemcpyAsync(ctx->h_io, ctx->d_io, 32, hipMemcpyDeviceToHost, s);
+    e = mapped ? hipSuccess : hipMemcpyAsync(ctx->h_io, ctx->d_io, 32, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
         e = hipStreamSynchronize(s);
     if (e != hipSuccess)
         return fail_hip(e, "result download");
+    const uint8_t *res = mapped ? ctx->h_map : ctx->h_io;
     if (op == 0) {
-        std::memcpy(tag_out, ctx->h_io, tag_len);
+        std::memcpy(tag_out, res, tag_len);
     } else {
         int32_t ok;
-        std::memcpy(&ok, ctx->h_io + 16, 4);
+        std::memcpy(&ok, res + 16, 4);
         *accept = ok == 1 ? 1 : 0;
     }
     return GCM_OK;

@@ -34,6 +34,12 @@ struct gcm_ctx {
     // context on the device; its address, looked up at context creation)
     void *d_scratch = nullptr;
     uint8_t *h_io = nullptr;  // pinned mirror
+    // one-shot results: pinned, host-coherent memory the kernels read the
+    // expected tag from and write the tag / flag to directly (d_map is its
+    // device address); NULL where the runtime cannot map it (then d_io and
+    // copies are used)
+    uint8_t *h_map = nullptr;
+    uint8_t *d_map = nullptr;
     // launch shape overrides (0 = automatic)
     uint32_t cfg_log2B = 0, cfg_waves = 0, cfg_gpc = 0, cfg_fanin = 0;
     // autotune caches: single messages keyed by (key bytes << 32 | floor(log2

@@ -636,6 +636,16 @@ class Server:
         self._keep = {}
 
     def submit(self, op: int, slot: int, iv: bytes, aad, inp, out, tag_d) -> int:
+        r = self.prepare(op, slot, iv, aad, inp, out, tag_d)
+        rid = self.submit_prepared(r)
+        self._keep[rid] = (aad, inp, out, tag_d)
+        return rid
+
+    @staticmethod
+    def prepare(op: int, slot: int, iv: bytes, aad, inp, out, tag_d) -> Request:
+        """The request record for submit_prepared (argument marshalling done
+        ahead of time); the caller keeps the tensors alive until the request
+        completes."""
         r = Request()
         r.op = op
         r.key_slot = slot
@@ -647,9 +657,11 @@ class Server:
         r.out_d = _dev(out) or None
         r.len = inp.numel()
         r.tag_d = _dev(tag_d)
+        return r
+
+    def submit_prepared(self, r: Request) -> int:
         rid = ctypes.c_uint64()
         _check(load().gcm_serve_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
-        self._keep[rid.value] = (aad, inp, out, tag_d)
         return rid.value
 
     def poll(self, rid: int):
