@@ -1043,11 +1043,11 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
     uint32_t hc = 0xffffffffu;  // upper counter bits `cur` belongs to (none yet)
     Ctr2 cur = {0, 0, 0, 0};
     const uint32_t loff = 16u * (uint32_t)lane;  // this lane's byte offset in a row
-    // Issue priority falls as the wave gets through its rows, so that waves
-    // the arbiter has left behind catch up and the compute unit stays full
-    // until its last tile ends.
+    // Issue priority falls as the wave gets through its rows (at 5/8, 3/4
+    // and 7/8 of them), so that waves the arbiter has left behind catch up
+    // and the compute unit stays full until its last tile ends.
     const uint32_t span = fb > r ? fb - r : 0u;
-    const uint32_t q1 = r + span / 4, q2 = r + span / 2, q3 = r + 3 * (span / 4);
+    const uint32_t q1 = r + 5 * (span / 8), q2 = r + 3 * (span / 4), q3 = r + 7 * (span / 8);
     __builtin_amdgcn_s_setprio(3);
     for (; r < fb; ++r) {
         if (r == q1)
