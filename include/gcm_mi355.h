@@ -254,8 +254,9 @@ typedef struct gcm_stream gcm_stream;
 
 /* op 0 encrypt / 1 decrypt-verify; the AAD (device, 16-byte aligned, may be
  * empty) is hashed here.  Allocates the stream's partials buffer (4 MiB,
- * doubled when full, 16 bytes per wave tile of every segment) from the
- * context budget. */
+ * 16 bytes per wave tile of every segment) from the context budget; an
+ * update or final that outgrows it doubles it, and that call waits for the
+ * stream once (the partials written so far move to the new buffer). */
 int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
                      const uint8_t *aad_d, uint64_t aad_len, gcm_stream **out, void *stream);
 

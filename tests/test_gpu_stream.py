@@ -153,3 +153,44 @@ def test_stream_misuse_errors(ctx):
     finally:
         torch.cuda.synchronize()
         ctx.key_release(slot)
+
+
+def test_stream_partials_buffer_grows_past_its_first_allocation(ctx):
+    """300 segments of 1 MiB (+ a ragged last one) leave more tile partials
+    than the stream's first 4 MiB partials buffer holds (with 64-block tiles
+    forced, 1,025 slots per segment: 307,500 against 262,144), so the buffer
+    is reallocated while segments are in flight; ciphertext and tag must
+    equal one call of the asynchronous path on the concatenated message
+    (itself checked against the oracle by the parity tests)."""
+    r = np.random.default_rng(6300)
+    key, iv = r.bytes(32), r.bytes(12)
+    aad = to_dev(r.integers(0, 256, 2880, dtype=np.uint8))
+    seg, nseg = 1 << 20, 300
+    n = seg * nseg + 1234
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6301)
+    pt = torch.empty(n, dtype=torch.uint8, device="cuda").random_(0, 256, generator=g)
+    slot = ctx.key_register(key)
+    ctx.set_launch(6, 0, 0)
+    try:
+        print(f"stream: {nseg + 1} segments, {n} bytes, 64-block tiles", flush=True)
+        st = ctx.stream_begin(0, slot, iv, aad)
+        ct = torch.empty_like(pt)
+        try:
+            for off in range(0, n, seg):
+                st.update(pt[off:off + seg], ct[off:off + seg])
+            tag = torch.zeros(16, dtype=torch.uint8, device="cuda")
+            st.final(tag, None)
+            torch.cuda.synchronize()
+        finally:
+            st.close()
+        ws = torch.zeros(ctx.workspace_size(n, aad.numel()), dtype=torch.uint8, device="cuda")
+        ct1 = torch.empty_like(pt)
+        tag1 = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        ctx.encrypt_async(slot, iv, aad, pt, ct1, tag1, ws)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_launch(0, 0, 0)
+        ctx.key_release(slot)
+    assert torch.equal(tag, tag1), "tag differs from the one-call path"
+    assert torch.equal(ct, ct1), "ciphertext differs from the one-call path"
