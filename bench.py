@@ -628,6 +628,22 @@ def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag
         mac_d = torch.zeros(16, dtype=torch.uint8, device=pt_d.device)
         ms_mac, tile_mac = timed(lambda: ctx.encrypt_async(slot, msg.iv, pt_d, None, None, mac_d, ws, stream),
                                  args.steps, 2)
+        # AES-128 (the paper's cipher) on the same buffer: the first 16 bytes
+        # of the key, same IV and AAD; round trip through decrypt-verify
+        slot128 = ctx.key_register(msg.key[:16], stream)
+        try:
+            tag128 = torch.zeros(16, dtype=torch.uint8, device=pt_d.device)
+            ms_128, tile_128 = timed(lambda: ctx.encrypt_async(slot128, msg.iv, aad_d, pt_d, back_d, tag128, ws,
+                                                               stream), args.steps, 2)
+            ok128 = torch.full((1,), -1, dtype=torch.int32, device=pt_d.device)
+            out128 = torch.empty_like(pt_d)
+            ctx.decrypt_verify_async(slot128, msg.iv, aad_d, back_d, tag128, out128, ok128, ws, stream)
+            torch.cuda.synchronize()
+            aes128_round_trip = int(ok128.item()) == 1 and bool(torch.equal(out128, pt_d))
+            del out128
+        finally:
+            torch.cuda.synchronize()
+            ctx.key_release(slot128)
         # the same message fed to the streamed API in 64 MiB segments
         seg = 64 << 20
         stag_d = torch.zeros(16, dtype=torch.uint8, device=pt_d.device)
@@ -717,6 +733,14 @@ def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag
         "ctr_only_gbs": round(n / (ms_ctr * 1e-3) / 1e9, 2),
         "gcm_over_ctr": round(ms_gcm / ms_ctr, 3),
         "ctr_output_equals_gcm_ciphertext": ctr_same,
+        "aes128": {
+            "scope": "AES-128-GCM encrypt+tag of the same buffer and AAD (key = first 16 bytes), resident key",
+            "ms": round(ms_128, 4),
+            "tile_kernel_ms": round(tile_128, 4),
+            "gbs": round(n / (ms_128 * 1e-3) / 1e9, 2),
+            "over_aes256": round(ms_128 / ms_gcm, 3),
+            "round_trip_accepted": aes128_round_trip,
+        },
         "ghash_only_gmac_ms": round(ms_mac, 4),
         "ghash_only_gmac_gbs": round(n / (ms_mac * 1e-3) / 1e9, 2),
         "streamed_64mib_segments_ms": round(ms_stream, 4),

@@ -1129,28 +1129,46 @@ __device__ __forceinline__ void stage_ttables(u32x4 *lds_v, const uint32_t *__re
 
 // The key's GHASH table of H^64 (64 KiB, LDS bytes [0, 64 KiB)) and its
 // lane fix-up windows (16 KiB, LDS bytes [128 KiB, 144 KiB)) from the key
-// slot, all of a thread's loads issued before its stores.  The caller adds
-// the barriers.
+// slot, all of a thread's loads issued before its stores.  In a workgroup
+// of 16 waves (128 VGPRs a thread) the thread index goes through an empty
+// asm so that the addresses are formed here: a caller that stages inside a
+// loop would otherwise hold them across the whole loop, spilled, and each
+// reload would wait for the previous load.  With fewer waves they stay in
+// registers.  The caller adds the barriers.
 template <int NT>
 __device__ __forceinline__ void stage_key_tables(u32x4 *lds_v, uint64_t slot)
 {
     const GLOBAL_AS u32x4 *tab = gptr<const u32x4>(slot + kSlotTab8Off);
     const GLOBAL_AS u32x4 *win = gptr<const u32x4>(slot + kSlotLaneWinOff);
-    constexpr int kTab = 4096, kWin = 1024;
-    constexpr int kPer = (kTab + kWin + NT - 1) / NT;
-    u32x4 st[kPer];
+    constexpr uint32_t kTab = 4096, kWin = 1024;
+    constexpr int kPerT = (int)((kTab + NT - 1) / NT), kPerW = (int)((kWin + NT - 1) / NT);
+    uint32_t tid = threadIdx.x;
+    if (NT >= 1024)
+        asm volatile("" : "+v"(tid));
+    u32x4 a[kPerT], b[kPerW];
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const uint32_t q = threadIdx.x + r * NT;
-        st[r] = q < (uint32_t)kTab ? tab[q] : q < (uint32_t)(kTab + kWin) ? win[q - kTab] : u32x4{0, 0, 0, 0};
+    for (int r = 0; r < kPerT; ++r) {
+        const uint32_t q = tid + (uint32_t)(r * NT);
+        if (kTab % NT == 0 || q < kTab)
+            a[r] = tab[q];
     }
 #pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-        const uint32_t q = threadIdx.x + r * NT;
-        if (q < (uint32_t)kTab)
-            lds_v[q] = st[r];
-        else if (q < (uint32_t)(kTab + kWin))
-            lds_v[8192 + (q - kTab)] = st[r];
+    for (int r = 0; r < kPerW; ++r) {
+        const uint32_t q = tid + (uint32_t)(r * NT);
+        if (kWin % NT == 0 || q < kWin)
+            b[r] = win[q];
+    }
+#pragma unroll
+    for (int r = 0; r < kPerT; ++r) {
+        const uint32_t q = tid + (uint32_t)(r * NT);
+        if (kTab % NT == 0 || q < kTab)
+            lds_v[q] = a[r];
+    }
+#pragma unroll
+    for (int r = 0; r < kPerW; ++r) {
+        const uint32_t q = tid + (uint32_t)(r * NT);
+        if (kWin % NT == 0 || q < kWin)
+            lds_v[8192 + q] = b[r];
     }
 }
 
@@ -1178,15 +1196,21 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
     if (GH && blockIdx.x == 0 && threadIdx.x == 0)
         counters[0] = 0;  // reject count for this launch (read by the zero-fill)
 
+    // A single message's key tables are staged here with the T-tables, while
+    // little else is live; a batch stages the tables of each work item's key
+    // in the loop (the first item's staging starts and ends with a barrier,
+    // which also publishes the T-tables).
     stage_ttables<WAVES * 64>(lds_v, te0g);
-    // with GHASH, the table staging of the first work item below starts and
-    // ends with a barrier, which also publishes the T-tables
-    if (!GH)
+    uint64_t cur_slot = 0;
+    if (GH && !BATCH) {
+        stage_key_tables<WAVES * 64>(lds_v, single.slot);
+        cur_slot = single.slot;
+    }
+    if (!GH || !BATCH)
         lds_barrier();
     const LaneK lk = lane_constants(threadIdx.x & 63);
     const GhK gk = gh_constants(threadIdx.x & 63);
 
-    uint64_t cur_slot = 0;
     const int wave = (int)uniform(threadIdx.x >> 6);  // wave-uniform: row bookkeeping stays scalar
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
         MsgDesc d;
@@ -1196,10 +1220,17 @@ __global__ __launch_bounds__(WAVES * 64) void k_gcm_tiles(const MsgDesc *__restr
             d = load_const<MsgDesc>(descs + w.msg);
             first = w.first_tile;
         } else {
+            // the descriptor's words pass through an empty asm on every item,
+            // so that nothing derived from them is hoisted out of this loop
+            // and held (or spilled) across all of it
             d = single;
+            uint32_t *dw = reinterpret_cast<uint32_t *>(&d);
+#pragma unroll
+            for (unsigned i = 0; i < sizeof(MsgDesc) / 4; ++i)
+                asm volatile("" : "+s"(dw[i]));
             first = (uint32_t)d.tile_lo + it * WAVES;
         }
-        if (GH && d.slot != cur_slot) {
+        if (GH && BATCH && d.slot != cur_slot) {
             lds_barrier();
             stage_key_tables<WAVES * 64>(lds_v, d.slot);
             cur_slot = d.slot;
@@ -1798,12 +1829,18 @@ __global__ __launch_bounds__(WAVES * 64) void k_siv_tiles(MsgDesc d, uint32_t n_
     const GhK gk = gh_constants(threadIdx.x & 63);
     const uint32_t wave = uniform(threadIdx.x >> 6);
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        const uint64_t t = d.tile_lo + (uint64_t)it * WAVES + wave;
-        if (t < d.tile_hi) {
-            if (d.nr == 10)
-                wave_tile_siv<10, PASS>(d, t, lds, lk, gk, te0g, partials);
+        // the descriptor made opaque per item, as in k_gcm_tiles
+        MsgDesc di = d;
+        uint32_t *dw = reinterpret_cast<uint32_t *>(&di);
+#pragma unroll
+        for (unsigned i = 0; i < sizeof(MsgDesc) / 4; ++i)
+            asm volatile("" : "+s"(dw[i]));
+        const uint64_t t = di.tile_lo + (uint64_t)it * WAVES + wave;
+        if (t < di.tile_hi) {
+            if (di.nr == 10)
+                wave_tile_siv<10, PASS>(di, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile_siv<14, PASS>(d, t, lds, lk, gk, te0g, partials);
+                wave_tile_siv<14, PASS>(di, t, lds, lk, gk, te0g, partials);
         }
     }
 }
