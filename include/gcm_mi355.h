@@ -253,10 +253,13 @@ int gcm_set_pipeline(gcm_ctx *ctx, uint64_t chunk_bytes);
 typedef struct gcm_stream gcm_stream;
 
 /* op 0 encrypt / 1 decrypt-verify; the AAD (device, 16-byte aligned, may be
- * empty) is hashed here.  Allocates the stream's partials buffer (4 MiB,
- * 16 bytes per wave tile of every segment) from the context budget; an
- * update or final that outgrows it doubles it, and that call waits for the
- * stream once (the partials written so far move to the new buffer). */
+ * empty) is hashed here.  The stream's partials buffer (at least 4 MiB, 16
+ * bytes per wave tile of every segment) and the pinned staging of its final
+ * call's descriptors are taken from those of an earlier destroyed stream of
+ * this context, else allocated (the device buffer from the context budget)
+ * when first needed; an update or final that outgrows the buffer doubles
+ * it, and that call waits for the stream once (the partials written so far
+ * move to the new buffer). */
 int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
                      const uint8_t *aad_d, uint64_t aad_len, gcm_stream **out, void *stream);
 
@@ -270,7 +273,12 @@ int gcm_stream_update(gcm_stream *st, const uint8_t *in_d, uint64_t len, uint8_t
  * accept flag (1/0) to accept_d (device). */
 int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_d, void *stream);
 
-/* Wait for the device, then free the stream's state. */
+/* Free the stream's state.  Its buffers stay with the context for later
+ * streams (up to four sets; released when an allocation would exceed the
+ * context budget, and by gcm_ctx_destroy), with an event recorded after its
+ * final call's kernels: a later stream's work waits for that event, so after
+ * a final call this returns without waiting.  A stream destroyed before its
+ * final call waits for the device first. */
 int gcm_stream_destroy(gcm_stream *st);
 
 /* ---------------------------------------------------------------- authenticated FITS container */

@@ -65,6 +65,8 @@ static const uint8_t kZeroIv[12] = {0};
 
 int gcm::ctx_alloc(gcm_ctx *ctx, void **p, uint64_t bytes)
 {
+    if (ctx->budget && ctx->used + bytes > ctx->budget && !ctx->stream_pool.empty())
+        stream_pool_release(ctx);
     if (ctx->budget && ctx->used + bytes > ctx->budget)
         return fail(GCM_E_NOMEM, "allocation of %llu bytes exceeds the context budget (%llu of %llu used)",
                     (unsigned long long)bytes, (unsigned long long)ctx->used, (unsigned long long)ctx->budget);
@@ -175,6 +177,7 @@ extern "C" int gcm_ctx_destroy(gcm_ctx *ctx)
         ctx_free(ctx, ctx->d_slots, kSlotBytes * ctx->n_slots);
         ctx_free(ctx, ctx->d_io, 256);
         ctx_free(ctx, ctx->d_ws, ctx->ws_bytes);
+        stream_pool_release(ctx);
         pipeline_release(ctx);
         for (auto &pr : ctx->prof_pending) {
             (void)hipEventDestroy(pr.first);

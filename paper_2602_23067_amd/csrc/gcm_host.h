@@ -62,6 +62,22 @@ struct gcm_ctx {
     uint64_t pipe_buf_bytes = 0;
     uint8_t *pipe_aad = nullptr;
     uint64_t pipe_aad_bytes = 0;
+    // buffers of destroyed streamed messages, kept for the next
+    // gcm_stream_begin so that a stream allocates nothing in the common
+    // case: the device partials buffer (counted in `used`), the pinned
+    // staging of the final call's segment descriptors, and an event recorded
+    // after the last work that used them (a later stream's work waits for
+    // it; the host waits for it before rewriting the staging or freeing).
+    // Released when an allocation would exceed the budget, and at context
+    // destruction.
+    struct StreamBufs {
+        uint8_t *d_part;
+        uint64_t part_bytes;
+        gcm::MsgDesc *h_desc;
+        uint64_t h_desc_bytes;
+        hipEvent_t ev;
+    };
+    std::vector<StreamBufs> stream_pool;
     std::mutex mu;
 };
 
@@ -111,6 +127,9 @@ int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_
 // Every single-message path (one-shot, asynchronous, counter mode, host
 // pipeline, streamed segments, GCM-SIV) and gcm_workspace_size use it.
 Shape message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len);
+// frees the buffers kept for streamed messages (caller holds ctx->mu; no
+// queued work uses them)
+void stream_pool_release(gcm_ctx *ctx);
 // Launch shape of a batch of n messages and `payload` bytes holding m GHASH
 // blocks in all: explicit settings, else the batch autotune cache, else the
 // heuristic (tile cap from the single-launch heuristic, 16 waves).

@@ -32,19 +32,30 @@ struct gcm_stream {
     uint64_t len = 0;      // payload bytes fed so far
     bool tail = false;     // a segment that was not a whole number of blocks has been fed
     bool closed = false;   // final was called
-    uint8_t iv[12] = {0};  // a 96-bit IV (j0 == nullptr)
-    uint8_t *d_j0 = nullptr;  // J0 for other IV lengths (16 B)
-    // counter block + reject list (256 B), then per segment its tile partials
-    // and the slot where its tile-0 wave leaves E_K(J0)
+    uint8_t iv[12] = {0};  // a 96-bit IV (!j0dev)
+    bool j0dev = false;    // J0 (other IV lengths) is in the header at kJ0Off
+    // header (256 B: the tile kernel's counter word, J0 at kJ0Off), then per
+    // segment its tile partials and the slot where its tile-0 wave leaves
+    // E_K(J0)
     uint8_t *d_part = nullptr;
     uint64_t part_bytes = 0;  // allocated
     uint64_t part_slots = 0;  // 16-byte slots in use after the header
     std::vector<MsgDesc> segs;
+    // pinned staging of the final call's segment descriptors
+    MsgDesc *h_desc = nullptr;
+    uint64_t h_desc_bytes = 0;
+    // recorded after the final call's kernels; it travels with the buffers
+    // (a pooled one may still mark an earlier stream's last work, which the
+    // host waits for before it rewrites the staging: ev_host_wait)
+    hipEvent_t ev = nullptr;
+    bool ev_host_wait = false;
+    bool ev_recorded = false;  // by this stream's final call
     uint32_t fanin = 2;
 };
 
 static constexpr uint64_t kHeader = 256;  // workspace_counter_bytes(1)
-static constexpr uint64_t kJ0Bytes = 256;
+static constexpr uint64_t kJ0Off = 128;   // 16 bytes of the header the kernels leave alone
+static constexpr size_t kPoolMax = 4;     // buffer sets kept for later streams
 
 // room for `slots` more 16-byte slots (and `extra` bytes after them); a
 // larger buffer takes over the slots written so far (stream-ordered copy)
@@ -58,7 +69,7 @@ static int part_reserve(gcm_stream *st, uint64_t slots, uint64_t extra, hipStrea
     int rc = ctx_alloc(st->ctx, reinterpret_cast<void **>(&p), want);
     if (rc)
         return rc;
-    if (st->part_slots) {
+    if (st->d_part && (st->part_slots || st->j0dev)) {
         hipError_t e = hipMemcpyAsync(p, st->d_part, kHeader + 16 * st->part_slots, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)
             e = hipStreamSynchronize(s);  // the old buffer is freed below
@@ -75,7 +86,8 @@ static int part_reserve(gcm_stream *st, uint64_t slots, uint64_t extra, hipStrea
 
 // A segment of d.m GHASH blocks (AAD blocks, data blocks, or the length block
 // alone): tile launch with the single-message shape for that size; its
-// partials and E_K(J0) slot go to the next free slots of the buffer.
+// partials and E_K(J0) slot go to the next free slots of the buffer (J0 is
+// read from the buffer's header, wherever the buffer is now).
 static int run_segment(gcm_stream *st, MsgDesc d, hipStream_t s)
 {
     gcm_ctx *ctx = st->ctx;
@@ -91,6 +103,7 @@ static int run_segment(gcm_stream *st, MsgDesc d, hipStream_t s)
     if (rc)
         return rc;
     d.tile_base = st->part_slots;
+    d.j0 = st->j0dev ? (uint64_t)(st->d_part + kJ0Off) : 0;
     rc = launch_tile_range(ctx, d, sh, st->d_part, s);
     if (rc)
         return rc;
@@ -104,14 +117,38 @@ static void segment_desc(const gcm_stream *st, MsgDesc *d)
 {
     fill_desc(d, st->op, st->iv, 0, 0, 0, 0, 0, 0, 0, (uint64_t)(st->ctx->d_slots + kSlotBytes * st->slot), st->nr, 6,
               16, 0);
-    d->j0 = (uint64_t)st->d_j0;
 }
 
+static void bufs_free(gcm_ctx *ctx, gcm_ctx::StreamBufs &b)
+{
+    if (b.ev) {
+        (void)hipEventSynchronize(b.ev);
+        (void)hipEventDestroy(b.ev);
+    }
+    ctx_free(ctx, b.d_part, b.part_bytes);
+    if (b.h_desc)
+        (void)hipHostFree(b.h_desc);
+}
+
+// The stream's buffers go back to the context's pool (or are freed when it
+// is full); queued work that still uses them finishes before st->ev
+// completes.  Caller holds ctx->mu.
 static void stream_free(gcm_stream *st)
 {
-    ctx_free(st->ctx, st->d_part, st->part_bytes);
-    ctx_free(st->ctx, st->d_j0, kJ0Bytes);
+    gcm_ctx *ctx = st->ctx;
+    gcm_ctx::StreamBufs b = {st->d_part, st->part_bytes, st->h_desc, st->h_desc_bytes, st->ev};
+    if (st->d_part && ctx->stream_pool.size() < kPoolMax)
+        ctx->stream_pool.push_back(b);
+    else
+        bufs_free(ctx, b);
     delete st;
+}
+
+void gcm::stream_pool_release(gcm_ctx *ctx)
+{
+    for (auto &b : ctx->stream_pool)
+        bufs_free(ctx, b);
+    ctx->stream_pool.clear();
 }
 
 extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const uint8_t *iv, size_t iv_len,
@@ -143,17 +180,35 @@ extern "C" int gcm_stream_begin(gcm_ctx *ctx, uint32_t op, uint32_t slot, const 
         st->slot = slot;
         st->nr = ctx->slot_nr[slot];
         st->aad_len = aad_len;
-        if (iv_len == 12) {
+        if (!ctx->stream_pool.empty()) {
+            // this stream's work waits for the last work on the buffers
+            const gcm_ctx::StreamBufs b = ctx->stream_pool.back();
+            ctx->stream_pool.pop_back();
+            st->d_part = b.d_part;
+            st->part_bytes = b.part_bytes;
+            st->h_desc = b.h_desc;
+            st->h_desc_bytes = b.h_desc_bytes;
+            st->ev = b.ev;
+            if (st->ev) {
+                st->ev_host_wait = true;
+                e = hipStreamWaitEvent(s, st->ev, 0);
+                if (e != hipSuccess)
+                    rc = fail_hip(e, "hipStreamWaitEvent");
+            }
+        }
+        if (rc == GCM_OK && iv_len == 12) {
             std::memcpy(st->iv, iv, 12);
-        } else {
-            // J0 = GHASH_H(IV || 0-pad || [len(IV)]_64) on the device
-            rc = ctx_alloc(ctx, reinterpret_cast<void **>(&st->d_j0), kJ0Bytes);
+        } else if (rc == GCM_OK) {
+            // J0 = GHASH_H(IV || 0-pad || [len(IV)]_64) on the device, into
+            // the partials buffer's header
+            st->j0dev = true;
+            rc = part_reserve(st, 0, 0, s);
             if (rc == GCM_OK) {
                 IvArg a;
                 std::memset(&a, 0, sizeof a);
                 a.len = (uint32_t)iv_len;
                 std::memcpy(a.b, iv, iv_len);
-                e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_j0, nullptr, s);
+                e = launch_j0(a, (uint64_t)(ctx->d_slots + kSlotBytes * slot), st->d_part + kJ0Off, nullptr, s);
                 if (e != hipSuccess)
                     rc = fail_hip(e, "J0 kernel launch");
             }
@@ -261,7 +316,30 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         if (after >= (1ull << kTab4Levels))
             return fail(GCM_E_TOOLONG, "streamed message of %llu GHASH blocks is beyond the lift tables",
                         (unsigned long long)after);
-        e = hipMemcpyAsync(d_descs, st->segs.data(), desc_bytes, hipMemcpyHostToDevice, s);
+        if (st->ev_host_wait) {
+            // an earlier stream's copy from the staging must have been read
+            e = hipEventSynchronize(st->ev);
+            if (e != hipSuccess)
+                return fail_hip(e, "hipEventSynchronize");
+            st->ev_host_wait = false;
+        }
+        if (st->h_desc_bytes < desc_bytes) {
+            // this stream's own staging (a pooled one comes back only after
+            // the device has finished with it)
+            if (st->h_desc)
+                (void)hipHostFree(st->h_desc);
+            st->h_desc = nullptr;
+            st->h_desc_bytes = 0;
+            const uint64_t want = std::max<uint64_t>(desc_bytes, 64 * sizeof(MsgDesc));
+            e = hipHostMalloc(reinterpret_cast<void **>(&st->h_desc), want, hipHostMallocDefault);
+            if (e != hipSuccess) {
+                st->h_desc = nullptr;
+                return fail_hip(e, "pinned descriptor staging");
+            }
+            st->h_desc_bytes = want;
+        }
+        std::memcpy(st->h_desc, st->segs.data(), desc_bytes);
+        e = hipMemcpyAsync(d_descs, st->h_desc, desc_bytes, hipMemcpyHostToDevice, s);
         if (e == hipSuccess)
             e = launch_combine(d_descs, k, nullptr, st->d_part + kHeader, reinterpret_cast<uint32_t *>(st->d_part),
                                st->fanin, s);
@@ -269,8 +347,13 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         if (e == hipSuccess)
             e = launch_fold(vals, k, st->d_part + kHeader + 16 * (last.tile_base + last.n_tiles), tag_d, accept_d,
                             st->op, 16, s);
+        if (e == hipSuccess && !st->ev)
+            e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
+        if (e == hipSuccess)
+            e = hipEventRecord(st->ev, s);
         if (e != hipSuccess)
             return fail_hip(e, "stream final kernels");
+        st->ev_recorded = true;
         st->closed = true;
         return GCM_OK;
     GCM_ABI_CATCH
@@ -284,7 +367,10 @@ extern "C" int gcm_stream_destroy(gcm_stream *st)
         gcm_ctx *ctx = st->ctx;
         std::lock_guard<std::mutex> g(ctx->mu);
         (void)hipSetDevice(ctx->device);
-        (void)hipDeviceSynchronize();  // the stream's queued kernels may still use its buffers
+        // after a final call the buffers' event marks their last use; a
+        // stream abandoned before it may still have work queued anywhere
+        if (!st->ev_recorded)
+            (void)hipDeviceSynchronize();
         stream_free(st);
         return GCM_OK;
     GCM_ABI_CATCH

@@ -194,3 +194,94 @@ def test_stream_partials_buffer_grows_past_its_first_allocation(ctx):
         ctx.key_release(slot)
     assert torch.equal(tag, tag1), "tag differs from the one-call path"
     assert torch.equal(ct, ct1), "ciphertext differs from the one-call path"
+
+
+def test_stream_buffers_are_reused_and_released_under_the_budget():
+    """A destroyed stream's partials buffer stays with the context for the
+    next stream and still counts against its budget; an allocation that would
+    exceed the budget releases it first.  Budget: the context's own tables
+    (AES tables, Frobenius tables, two key slots, the result block) plus one
+    4 MiB partials buffer and half a MiB: the one-shot call's 1 MiB workspace
+    fits only once the kept buffer is released, after which a new stream's
+    4 MiB no longer fits (GCM_E_NOMEM, nothing launched)."""
+    slot_bytes = 2048 + 65536 + 40 * 8192 + 16384
+    base = 5 * 256 * 4 + 47 * 4096 * 16 + 2 * slot_bytes + 256
+    c = gcm.Context(device=0, hbm_budget=base + (4 << 20) + (512 << 10), key_slots=2)
+    try:
+        r = np.random.default_rng(6400)
+        key, iv = r.bytes(16), r.bytes(12)
+        pt = r.integers(0, 256, 3 * 4096 + 5, dtype=np.uint8)
+        rct, rtag = oracle.gcm_encrypt(key, iv, b"", pt)
+        slot = c.key_register(key)
+        for rep in range(2):  # the second stream runs on the first one's buffer
+            print(f"stream rep {rep}", flush=True)
+            ct, tag = _stream_encrypt(c, slot, iv, np.zeros(0, np.uint8), pt, [4096, 8192])
+            assert np.array_equal(ct, rct) and tag == rtag
+        x = to_dev(pt)
+        y = torch.empty_like(x)
+        tag1 = c.encrypt(key, iv, None, x, y)  # needs the kept buffer's budget
+        torch.cuda.synchronize()
+        assert tag1 == rtag and np.array_equal(host(y), rct)
+        st = c.stream_begin(0, slot, iv)
+        try:
+            with pytest.raises(gcm.GcmError) as e:
+                st.update(x, y)
+            assert e.value.code == gcm.GCM_E_NOMEM
+        finally:
+            st.close()
+    finally:
+        torch.cuda.synchronize()
+        c.close()
+
+
+def test_stream_buffers_reused_across_hip_streams_without_waiting():
+    """Message A (48 MiB, still running) is closed right after its final call;
+    message B begins on another HIP stream at once and takes A's buffers from
+    the context: B's kernels must wait for A's last work (the buffers' event),
+    so both tags and ciphertexts equal one call of the asynchronous path on
+    each message (itself checked against the oracle by the parity tests)."""
+    r = np.random.default_rng(6500)
+    key = r.bytes(32)
+    n_a, n_b = 48 << 20, (3 << 20) + 100
+    g = torch.Generator(device="cuda")
+    g.manual_seed(6501)
+    pa = torch.empty(n_a, dtype=torch.uint8, device="cuda").random_(0, 256, generator=g)
+    pb = torch.empty(n_b, dtype=torch.uint8, device="cuda").random_(0, 256, generator=g)
+    iv_a, iv_b = r.bytes(12), r.bytes(20)
+    c = gcm.Context(device=0, key_slots=4)
+    s2 = torch.cuda.Stream()
+    try:
+        slot = c.key_register(key)
+        torch.cuda.synchronize()
+        outs = []
+        for _ in range(2):  # the second round reuses the buffers the first one left
+            ca, cb = torch.empty_like(pa), torch.empty_like(pb)
+            ta = torch.zeros(16, dtype=torch.uint8, device="cuda")
+            tb = torch.zeros(16, dtype=torch.uint8, device="cuda")
+            st = c.stream_begin(0, slot, iv_a)
+            for off in range(0, n_a, 16 << 20):
+                st.update(pa[off:off + (16 << 20)], ca[off:off + (16 << 20)])
+            st.final(ta)
+            st.close()
+            s2.wait_stream(torch.cuda.current_stream())  # B's input was made on the default stream
+            with torch.cuda.stream(s2):
+                st = c.stream_begin(0, slot, iv_b, None, s2)
+                st.update(pb[:1 << 20], cb[:1 << 20], s2)
+                st.update(pb[1 << 20:], cb[1 << 20:], s2)
+                st.final(tb, None, s2)
+                st.close()
+            outs.append((ca, cb, ta, tb))
+        torch.cuda.synchronize()
+        ws = torch.zeros(c.workspace_size(n_a, 0), dtype=torch.uint8, device="cuda")
+        ra, rb = torch.empty_like(pa), torch.empty_like(pb)
+        rta = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        rtb = torch.zeros(16, dtype=torch.uint8, device="cuda")
+        c.encrypt_async(slot, iv_a, None, pa, ra, rta, ws)
+        c.encrypt_async(slot, iv_b, None, pb, rb, rtb, ws)
+        torch.cuda.synchronize()
+        for ca, cb, ta, tb in outs:
+            assert torch.equal(ta, rta) and torch.equal(ca, ra), "message A"
+            assert torch.equal(tb, rtb) and torch.equal(cb, rb), "message B"
+    finally:
+        torch.cuda.synchronize()
+        c.close()
