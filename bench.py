@@ -657,10 +657,11 @@ def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag
             finally:
                 st.close()  # no wait: its buffers serve the next message once this one's work is done
 
-        ms_stream, _ = timed(streamed, max(2, min(10, args.steps // 2)), 1, False)
+        ms_stream, _ = timed(streamed, max(2, min(20, args.steps // 2)), 2, False)
+        stream_steps = sorted(timed.last_steps)
         # the one call it is compared with, timed the same way (no tile events)
         ms_one, _ = timed(lambda: ctx.encrypt_async(slot, msg.iv, aad_d, pt_d, ct_d, tag_d, ws, stream),
-                          max(2, min(10, args.steps // 2)), 1, False)
+                          max(2, min(20, args.steps // 2)), 2, False)
         torch.cuda.synchronize()
         stream_same = bool(torch.equal(stag_d, gcm_tag)) and bool(torch.equal(back_d, ct_d))
 
@@ -749,6 +750,8 @@ def run_modes(args, ctx, msg, gcm, torch, stream, pt_d, aad_d, ct_d, back_d, tag
         "streamed_64mib_segments_gbs": round(n / (ms_stream * 1e-3) / 1e9, 2),
         "streamed_equals_one_call": stream_same,
         "streamed_over_one_call_rate": round(ms_one / ms_stream, 3),
+        "streamed_step_ms_min_p50_max": [round(stream_steps[0], 4), round(stream_steps[len(stream_steps) // 2], 4),
+                                         round(stream_steps[-1], 4)],
         "gcm_siv": {
             "scope": "RFC 8452 AES-256-GCM-SIV on the same buffer and AAD, device-resident, per-call key derivation",
             "encrypt_ms": round(ms_siv_enc, 4),
@@ -848,6 +851,7 @@ def main():
         ctx.profile_enable(False)
         launches, tile_ms = ctx.profile_read()
         step_ms[:] = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+        timed.last_steps = list(step_ms)
         return ev[0].elapsed_time(ev[steps]) / steps, tile_ms / max(1, launches)
 
     # The GPU's clock settles over its first few dozen launches after the idle

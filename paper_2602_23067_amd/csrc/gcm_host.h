@@ -190,9 +190,12 @@ int max_groups_per_cu(int waves);
 hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *single, const void *partials,
                           uint32_t *counters, uint32_t fanin, hipStream_t s);
 hipError_t launch_j0(const IvArg &iv, uint64_t slot, void *j0_out, void *y_zero, hipStream_t s);
-// streamed message: XOR of k lifted segment values and E_K(J0) -> tag (op 0) or accept flag (op 1)
+// streamed message: XOR of k lifted segment values, the length block's term
+// lenblk * H (lenblk: memory-order words, or NULL when it is one of the
+// values; H from the key slot at device address `slot`) and E_K(J0) -> tag
+// (op 0) or accept flag (op 1)
 hipError_t launch_fold(const void *vals, uint32_t k, const void *ekj0, uint8_t *tag, int32_t *ok, uint32_t op,
-                       uint32_t tag_len, hipStream_t s);
+                       uint32_t tag_len, uint64_t slot, const uint32_t lenblk[4], hipStream_t s);
 // device address of the fixed scratch array on `device` (looked up once per device)
 hipError_t scratch_address(int device, void **out);
 hipError_t launch_zerofill(const MsgDesc *descs, const MsgDesc *single, const uint32_t *counters, uint32_t grid,

@@ -1422,13 +1422,19 @@ __global__ __launch_bounds__(kCombineThreads) void k_gcm_combine(const MsgDesc *
 // compares them without early exit and writes the accept flag.
 __global__ __launch_bounds__(64) void k_gcm_fold(const u32x4 *__restrict__ vals, uint32_t k,
                                                  const u32x4 *__restrict__ ekj0, uint8_t *tag, int32_t *ok,
-                                                 uint32_t op, uint32_t tag_len)
+                                                 uint32_t op, uint32_t tag_len, uint64_t slot, u32x4 lenblk)
 {
     const uint32_t lane = threadIdx.x;
     u32x4 acc = {0, 0, 0, 0};
     for (uint32_t j = lane; j < k; j += 64)
         acc ^= vals[j];
     acc = wave_xor_reduce(acc);
+    if (slot) {
+        // GHASH's last block, the length block L, enters as L * H (the
+        // slot's nibble table of H^(2^0)); the values above were lifted past it
+        const u32x4 *g4 = reinterpret_cast<const u32x4 *>(slot + kSlotTab4Off);
+        acc ^= mul_tab4_half(lenblk, g4, lane & 31u, lane < 32);
+    }
     if (lane != 0)
         return;
     const u32x4 t = acc ^ *ekj0;
@@ -1984,10 +1990,11 @@ hipError_t launch_combine(const MsgDesc *descs, uint32_t n_msgs, const MsgDesc *
 }
 
 hipError_t launch_fold(const void *vals, uint32_t k, const void *ekj0, uint8_t *tag, int32_t *ok, uint32_t op,
-                       uint32_t tag_len, hipStream_t s)
+                       uint32_t tag_len, uint64_t slot, const uint32_t lenblk[4], hipStream_t s)
 {
+    const u32x4 l = lenblk ? u32x4{lenblk[0], lenblk[1], lenblk[2], lenblk[3]} : u32x4{0, 0, 0, 0};
     hipLaunchKernelGGL(k_gcm_fold, dim3(1), dim3(64), 0, s, reinterpret_cast<const u32x4 *>(vals), k,
-                       reinterpret_cast<const u32x4 *>(ekj0), tag, ok, op, tag_len);
+                       reinterpret_cast<const u32x4 *>(ekj0), tag, ok, op, tag_len, lenblk ? slot : 0, l);
     return hipGetLastError();
 }
 

@@ -7,10 +7,11 @@
 // therefore runs only the tile kernel over its segment (its counters start
 // after the blocks fed so far) and leaves the segment's tile partials in the
 // stream's partials buffer; nothing depends on the previous segment.  The
-// final call adds the length block as one more segment, reduces every
-// segment's partials in one batched combine launch (each segment's value
-// lifted by H^(blocks after it)), and one small kernel XORs the lifted values
-// with E_K(J0) into the tag or the accept flag.
+// final call reduces every segment's partials in one batched combine launch
+// (each segment's value lifted by H^(blocks after it), the length block
+// included), and one small kernel XORs the lifted values, the length block's
+// term L * H and E_K(J0) into the tag or the accept flag.  (A message with
+// neither AAD nor payload runs its length block as a segment of its own.)
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -287,18 +288,28 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         hipError_t e = hipSetDevice(ctx->device);
         if (e != hipSuccess)
             return fail_hip(e, "hipSetDevice");
-        // the last segment: the length block [8|A|]_64 || [8|C|]_64 alone; its
-        // tile-0 wave also leaves E_K(J0)
-        MsgDesc d;
-        segment_desc(st, &d);
-        d.aad_len = st->aad_len;
-        d.len = st->len;
-        d.na = 0;
-        d.n = 0;
-        d.m = 1;
-        int rc = run_segment(st, d, s);
-        if (rc)
-            return rc;
+        // GHASH's last block, the length block [8|A|]_64 || [8|C|]_64: with
+        // nothing before it (no AAD, no payload) it runs as a segment of its
+        // own, whose tile-0 wave also leaves E_K(J0); otherwise the fold
+        // kernel adds its term L * H, and E_K(J0) is the one the first
+        // segment's tile-0 wave left
+        const uint64_t abits = st->aad_len * 8, cbits = st->len * 8;
+        const uint32_t lenblk[4] = {__builtin_bswap32((uint32_t)(abits >> 32)), __builtin_bswap32((uint32_t)abits),
+                                    __builtin_bswap32((uint32_t)(cbits >> 32)), __builtin_bswap32((uint32_t)cbits)};
+        const bool len_seg = st->segs.empty();
+        int rc = GCM_OK;
+        if (len_seg) {
+            MsgDesc d;
+            segment_desc(st, &d);
+            d.aad_len = st->aad_len;
+            d.len = st->len;
+            d.na = 0;
+            d.n = 0;
+            d.m = 1;
+            rc = run_segment(st, d, s);
+            if (rc)
+                return rc;
+        }
         const uint32_t k = (uint32_t)st->segs.size();
         const uint64_t desc_bytes = (uint64_t)k * sizeof(MsgDesc);
         rc = part_reserve(st, k, desc_bytes + 16, s);
@@ -307,7 +318,7 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         uint8_t *vals = st->d_part + kHeader + 16 * st->part_slots;
         MsgDesc *d_descs = reinterpret_cast<MsgDesc *>(vals + 16 * (uint64_t)k);
         // segment j's value is lifted by H^(GHASH blocks after it)
-        uint64_t after = 0;
+        uint64_t after = len_seg ? 0 : 1;
         for (uint32_t j = k; j-- > 0;) {
             st->segs[j].yout = (uint64_t)(vals + 16 * (uint64_t)j);
             st->segs[j].lift = after;
@@ -343,10 +354,10 @@ extern "C" int gcm_stream_final(gcm_stream *st, uint8_t *tag_d, int32_t *accept_
         if (e == hipSuccess)
             e = launch_combine(d_descs, k, nullptr, st->d_part + kHeader, reinterpret_cast<uint32_t *>(st->d_part),
                                st->fanin, s);
-        const MsgDesc &last = st->segs.back();
+        const MsgDesc &first = st->segs.front();
         if (e == hipSuccess)
-            e = launch_fold(vals, k, st->d_part + kHeader + 16 * (last.tile_base + last.n_tiles), tag_d, accept_d,
-                            st->op, 16, s);
+            e = launch_fold(vals, k, st->d_part + kHeader + 16 * (first.tile_base + first.n_tiles), tag_d, accept_d,
+                            st->op, 16, first.slot, len_seg ? nullptr : lenblk, s);
         if (e == hipSuccess && !st->ev)
             e = hipEventCreateWithFlags(&st->ev, hipEventDisableTiming);
         if (e == hipSuccess)
