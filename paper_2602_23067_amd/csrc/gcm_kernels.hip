@@ -1835,18 +1835,12 @@ __global__ __launch_bounds__(WAVES * 64) void k_siv_tiles(MsgDesc d, uint32_t n_
     const GhK gk = gh_constants(threadIdx.x & 63);
     const uint32_t wave = uniform(threadIdx.x >> 6);
     for (uint32_t it = blockIdx.x; it < n_items; it += gridDim.x) {
-        // the descriptor made opaque per item, as in k_gcm_tiles
-        MsgDesc di = d;
-        uint32_t *dw = reinterpret_cast<uint32_t *>(&di);
-#pragma unroll
-        for (unsigned i = 0; i < sizeof(MsgDesc) / 4; ++i)
-            asm volatile("" : "+s"(dw[i]));
-        const uint64_t t = di.tile_lo + (uint64_t)it * WAVES + wave;
-        if (t < di.tile_hi) {
-            if (di.nr == 10)
-                wave_tile_siv<10, PASS>(di, t, lds, lk, gk, te0g, partials);
+        const uint64_t t = d.tile_lo + (uint64_t)it * WAVES + wave;
+        if (t < d.tile_hi) {
+            if (d.nr == 10)
+                wave_tile_siv<10, PASS>(d, t, lds, lk, gk, te0g, partials);
             else
-                wave_tile_siv<14, PASS>(di, t, lds, lk, gk, te0g, partials);
+                wave_tile_siv<14, PASS>(d, t, lds, lk, gk, te0g, partials);
         }
     }
 }
