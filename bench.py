@@ -270,7 +270,7 @@ def run_decrypt_config4(ctx, gcm, workloads, torch, n_files, side, steps):
     ms = e0.elapsed_time(e1) / steps
     ok = base[lay.ok_base:lay.ok_base + 4 * n_files].view(torch.int32).cpu().numpy()
     rejected = set(int(i) for i in np.nonzero(ok == 0)[0])
-    zero_ok = all(not bool(base[lay.out_off[f]:lay.out_off[f] + size].any()) for f in list(rejected)[:8])
+    zero_ok = all(not bool(base[lay.out_off[f]:lay.out_off[f] + size].any()) for f in sorted(rejected))
     b.close()
     for s_ in slots:
         ctx.key_release(s_)
