@@ -351,6 +351,15 @@ SlotView gcm::slot_view(const gcm_ctx *ctx)
     return v;
 }
 
+// groups of the tile kernel a compute unit holds (occupancy query, once per
+// process: every device is the same part)
+static uint32_t groups_per_cu(uint32_t waves)
+{
+    static const uint32_t g8 = (uint32_t)max_groups_per_cu(8), g12 = (uint32_t)max_groups_per_cu(12),
+                          g16 = (uint32_t)max_groups_per_cu(16);
+    return waves == 8 ? g8 : waves == 12 ? g12 : waves == 16 ? g16 : (uint32_t)max_groups_per_cu((int)waves);
+}
+
 Shape gcm::message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len)
 {
     Shape sh;
@@ -363,11 +372,19 @@ Shape gcm::message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, u
             tuned = true;
         }
     }
-    sh.waves = ctx->cfg_waves ? ctx->cfg_waves : tuned ? t.waves : 16;
-    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (tuned && t.gpc) ? t.gpc : (uint32_t)max_groups_per_cu((int)sh.waves);
+    const uint64_t m = ghash_blocks(aad_len, len);
+    if (ctx->cfg_waves)
+        sh.waves = ctx->cfg_waves;
+    else if (tuned)
+        sh.waves = t.waves;
+    else if (ctx->cfg_log2B || ctx->cfg_gpc)
+        sh.waves = 16;
+    else
+        sh.waves = heuristic_waves(m, (uint64_t)ctx->cu_count, groups_per_cu);
+    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (tuned && t.gpc) ? t.gpc : groups_per_cu(sh.waves);
     sh.log2B = ctx->cfg_log2B ? ctx->cfg_log2B
                : tuned        ? t.log2B
-                              : heuristic_log2B(ghash_blocks(aad_len, len), (uint64_t)ctx->cu_count * sh.gpc * sh.waves);
+                              : heuristic_log2B(m, (uint64_t)ctx->cu_count * sh.gpc * sh.waves);
     sh.fanin = ctx->cfg_fanin ? ctx->cfg_fanin : (tuned && t.fanin) ? t.fanin : 2;
     return sh;
 }

@@ -116,6 +116,54 @@ inline uint32_t heuristic_log2B(uint64_t m, uint64_t resident)
     return best_l;
 }
 
+// Rows of 64 blocks that the busiest compute unit runs for one message
+// launched with tiles of 2^l blocks in workgroups of `waves` waves: item k
+// (tiles [k*waves, (k+1)*waves)) goes to workgroup k mod grid, grid =
+// min(items, cus * gpc), and each tile costs its rows plus about one row of
+// fix-up.  Used to compare shapes, not to predict times.
+inline uint64_t busiest_cu_rows(uint64_t m, uint32_t l, uint32_t waves, uint64_t cus, uint32_t gpc)
+{
+    const uint64_t B = 1ull << l, T = (m + B - 1) / B;
+    const uint64_t items = (T + waves - 1) / waves;
+    const uint64_t slots = cus * (gpc ? gpc : 1);
+    const uint64_t grid = items < slots ? items : slots;
+    uint64_t tiles = 0;  // workgroup 0's, its items k*grid
+    for (uint64_t k = 0; k * grid < items; ++k) {
+        const uint64_t first = k * grid * waves;
+        tiles += T - first < waves ? T - first : waves;
+    }
+    return tiles * (B / 64 + 1) * (gpc ? gpc : 1);
+}
+
+// Waves per workgroup for one message (tile size from heuristic_log2B for
+// that many waves).  Sixteen unless the message has fewer tiles than the
+// chip has wave slots: then 16-wave workgroups would crowd its tiles onto a
+// fraction of the compute units, and 12 or 8 waves a workgroup spread them
+// over more.  Among 16, 12 and 8 the one whose busiest compute unit has the
+// fewest rows (busiest_cu_rows) wins, ties to more waves.  gpc(w): groups a
+// compute unit holds with w waves.
+template <typename Gpc>
+inline uint32_t heuristic_waves(uint64_t m, uint64_t cus, Gpc gpc)
+{
+    const uint32_t g16 = gpc(16);
+    const uint32_t l16 = heuristic_log2B(m, cus * g16 * 16);
+    const uint64_t t16 = (m + (1ull << l16) - 1) >> l16;
+    if ((t16 + 15) / 16 >= cus * g16)
+        return 16;
+    uint32_t best_w = 16;
+    uint64_t best = busiest_cu_rows(m, l16, 16, cus, g16);
+    for (uint32_t w : {12u, 8u}) {
+        const uint32_t g = gpc(w);
+        const uint32_t l = heuristic_log2B(m, cus * g * w);
+        const uint64_t load = busiest_cu_rows(m, l, w, cus, g);
+        if (load < best) {
+            best = load;
+            best_w = w;
+        }
+    }
+    return best_w;
+}
+
 // Tile size of one message inside a batch: about one workgroup item (waves
 // tiles) for small messages, at most 2^cap blocks per tile for large ones,
 // so the persistent workgroups see items of similar cost.  cap: 6..20.

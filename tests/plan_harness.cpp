@@ -266,6 +266,31 @@ int main()
         const uint64_t T = (m + (1ull << l) - 1) >> l;
         CHECK(l >= 8 || T <= resident);
     }
+    // 5. waves per workgroup for one message: 16 once the message fills the
+    // chip's wave slots, otherwise the shape whose busiest compute unit has
+    // the fewest rows; never more rows there than the 16-wave shape
+    {
+        const auto gpc1 = [](uint32_t) { return 1u; };
+        for (int it = 0; it < 20000; ++it) {
+            const uint64_t m = it < 200 ? (uint64_t)it * 97 + 1 : 1 + r() % ((1ull << 27) + 1);
+            const uint64_t cus = 1 + r() % 304;
+            const uint32_t w = heuristic_waves(m, cus, gpc1);
+            CHECK(w == 8 || w == 12 || w == 16);
+            const uint32_t l16 = heuristic_log2B(m, cus * 16);
+            const uint64_t t16 = (m + (1ull << l16) - 1) >> l16;
+            if ((t16 + 15) / 16 >= cus)
+                CHECK(w == 16);
+            const uint32_t l = heuristic_log2B(m, cus * w);
+            CHECK(busiest_cu_rows(m, l, w, cus, 1) <= busiest_cu_rows(m, l16, 16, cus, 1));
+        }
+        // the measured cases on 256 compute units (AES-256, 2880-byte AAD: 180 blocks)
+        CHECK(heuristic_waves((1ull << 16) + 181, 256, gpc1) == 8);   // 1 MiB
+        CHECK(heuristic_waves((2ull << 16) + 181, 256, gpc1) == 12);  // 2 MiB
+        CHECK(heuristic_waves((4ull << 16) + 181, 256, gpc1) == 12);  // 4 MiB
+        CHECK(heuristic_waves((16ull << 16) + 1, 256, gpc1) == 16);   // 16 MiB
+        CHECK(heuristic_waves((64ull << 16) + 1, 256, gpc1) == 16);   // 64 MiB
+        CHECK(heuristic_waves(67109040ull + 181, 256, gpc1) == 16);   // 1 GiB
+    }
     std::printf("plan harness: OK\n");
     return 0;
 }
