@@ -353,7 +353,7 @@ SlotView gcm::slot_view(const gcm_ctx *ctx)
 
 // groups of the tile kernel a compute unit holds (occupancy query, once per
 // process: every device is the same part)
-static uint32_t groups_per_cu(uint32_t waves)
+uint32_t gcm::groups_per_cu(uint32_t waves)
 {
     static const uint32_t g8 = (uint32_t)max_groups_per_cu(8), g12 = (uint32_t)max_groups_per_cu(12),
                           g16 = (uint32_t)max_groups_per_cu(16);

@@ -127,6 +127,8 @@ int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_
 // Every single-message path (one-shot, asynchronous, counter mode, host
 // pipeline, streamed segments, GCM-SIV) and gcm_workspace_size use it.
 Shape message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len);
+// groups of the tile kernel (`waves` waves each) a compute unit holds
+uint32_t groups_per_cu(uint32_t waves);
 // frees the buffers kept for streamed messages (caller holds ctx->mu; no
 // queued work uses them)
 void stream_pool_release(gcm_ctx *ctx);

@@ -32,13 +32,16 @@ constexpr uint64_t kSivStateOff = kSlotBytes;         // 16 B POLYVAL-as-GHASH v
 constexpr uint64_t kSivTilesOff = kSlotBytes + 256;   // counters and partials
 
 // GCM-SIV's tile kernels take the untuned single-message shape (the
-// autotuner times GCM's kernels, not these); explicit gcm_set_launch
-// settings apply.
+// autotuner times GCM's kernels, not these): the wave count that spreads a
+// message over the most compute units, then the tile size; explicit
+// gcm_set_launch settings apply.
 Shape siv_shape(const gcm_ctx *ctx, uint64_t m)
 {
     Shape sh;
-    sh.waves = ctx->cfg_waves ? ctx->cfg_waves : 16;
-    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : (uint32_t)max_groups_per_cu((int)sh.waves);
+    sh.waves = ctx->cfg_waves                       ? ctx->cfg_waves
+               : (ctx->cfg_log2B || ctx->cfg_gpc) ? 16u
+                                                  : heuristic_waves(m, (uint64_t)ctx->cu_count, groups_per_cu);
+    sh.gpc = ctx->cfg_gpc ? ctx->cfg_gpc : groups_per_cu(sh.waves);
     sh.log2B = ctx->cfg_log2B ? ctx->cfg_log2B : heuristic_log2B(m, (uint64_t)ctx->cu_count * sh.gpc * sh.waves);
     sh.fanin = ctx->cfg_fanin ? ctx->cfg_fanin : 2;
     return sh;
