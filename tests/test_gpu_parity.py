@@ -58,6 +58,20 @@ def test_config1_parity(ctx):
     _check_case(ctx, m.key, m.iv, m.aad, m.data)
 
 
+# the planner's own shapes for messages that do not fill the chip: 8- or
+# 12-wave workgroups below a few MiB, 16 above (every one a distinct
+# tile-size / wave-count choice on a 256-CU part), with ragged tails
+@pytest.mark.parametrize("n", [(1 << 20) + 17, 2 << 20, (3 << 20) + 5, 4 << 20, (6 << 20) + 16, (12 << 20) + 1])
+def test_default_shapes_by_size(ctx, n):
+    r = workloads.rng_for(5000 + n % 997)
+    key = workloads.random_bytes(r, 32).tobytes()
+    iv = workloads.random_bytes(r, 12).tobytes()
+    aad = workloads.random_bytes(r, 2880)
+    pt = workloads.random_bytes(r, n)
+    print(f"default shape: len={n}", flush=True)
+    _check_case(ctx, key, iv, aad, pt)
+
+
 @pytest.mark.parametrize("log2B", [6, 8])
 def test_tail_sweep(ctx, log2B):
     ctx.set_launch(log2B, 8, 1)
