@@ -58,18 +58,21 @@ def parse():
     ap.add_argument("--encrypt-only", action="store_true",
                     help="time only the config-2 encrypt steps (and the device copy): no decrypt-verify timing, "
                          "no one-shot latency loop, no other workloads (for kernel traces of the timed launches)")
+    ap.add_argument("--key-bits", type=int, default=256, choices=(128, 256),
+                    help="key size of the config-2 steps (the headline workload is AES-256; 128 is for profiling "
+                         "the paper's cipher on the same buffer: its key is the first 16 bytes of the AES-256 key)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run three plain 1 GiB device-to-device copies first (HBM counter calibration)")
     return ap.parse_args()
 
 
-def profile_record():
+def profile_record(key_bits=256):
     """The committed rocprofv3 counter summary of the tile kernel on this
     workload, if it was taken on this exact kernel source (else None: the
     counters would describe another kernel)."""
     import hashlib
 
-    prof = os.path.join(ROOT, "profiles", "k_gcm_tiles_fits1gib_aes256_traffic.json")
+    prof = os.path.join(ROOT, "profiles", f"k_gcm_tiles_fits1gib_aes{key_bits}_traffic.json")
     src = os.path.join(ROOT, "paper_2602_23067_amd", "csrc", "gcm_kernels.hip")
     try:
         with open(prof) as f:
@@ -81,14 +84,14 @@ def profile_record():
     return rec if rec.get("kernel_source_sha256") == digest else None
 
 
-def measured_traffic(algorithmic_bytes):
+def measured_traffic(algorithmic_bytes, key_bits=256):
     """HBM bytes per launch of the tile kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (see profile_record)."""
-    rec = profile_record()
+    rec = profile_record(key_bits)
     return int(rec["traffic_bytes_per_launch"]) if rec else None
 
 
-def issue_roofline():
+def issue_roofline(key_bits=256):
     """VALU and LDS issue of the tile kernel against the chip's issue rate at
     the clock it held: per 64-block row, the VALU wave-instructions, the LDS
     index-active cycles (2 per b32 lookup, 4 per b128) and the kernel's own
@@ -96,7 +99,7 @@ def issue_roofline():
     summary of this kernel source; busy = work cycles / kernel cycles, one
     wave64 VALU instruction per clock per CU.  None if the counters were
     taken on another kernel source."""
-    rec = profile_record()
+    rec = profile_record(key_bits)
     if not rec or "valu_busy" not in rec:
         return None
     return {
@@ -105,7 +108,7 @@ def issue_roofline():
         "kernel_cycles_per_row_per_cu": rec["kernel_cycles_per_row_per_cu"],
         "valu_busy": rec["valu_busy"],
         "lds_busy": rec["lds_busy"],
-        "source": "profiles/k_gcm_tiles_fits1gib_aes256_traffic.json (rocprofv3 counters)",
+        "source": f"profiles/k_gcm_tiles_fits1gib_aes{key_bits}_traffic.json (rocprofv3 counters)",
     }
 
 
@@ -802,6 +805,8 @@ def main():
         del a, b_
     print(f"[bench] generating FITS-shaped input {args.ny}x{args.nx}", file=sys.stderr, flush=True)
     msg = workloads.config2(ny=args.ny, nx=args.nx)
+    if args.key_bits == 128:
+        msg.key = msg.key[:16]
     n = msg.data.size
     aad_len = msg.aad.size
     pt_d = torch.from_numpy(msg.data).to(dev)
@@ -964,11 +969,11 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {
-            "workload": "AES-256-GCM encrypt+tag of one FITS-shaped buffer: 16384x16384 float32 Gaussian sky "
+            "workload": f"AES-{args.key_bits}-GCM encrypt+tag of one FITS-shaped buffer: 16384x16384 float32 Gaussian sky "
                         "noise + 1e4 point sources, big-endian, padded to a 2880 multiple; AAD = 2880-byte header",
             "bytes": n,
             "aad_bytes": aad_len,
-            "key_bits": 256,
+            "key_bits": args.key_bits,
             "parallelism": "single GPU",
         },
         "hbm_traffic_gbs": round(traffic / (ms_enc * 1e-3) / 1e9, 2),
@@ -986,7 +991,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(tile_gbs / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(tile_bytes) if (args.ny, args.nx) == (16384, 16384) else None,
+            "traffic": measured_traffic(tile_bytes, args.key_bits) if (args.ny, args.nx) == (16384, 16384) else None,
             "tile_kernel_ms": round(tile_ms, 4),
             "algorithmic_bytes_per_launch": tile_bytes,
         },
@@ -1007,7 +1012,7 @@ def main():
             "clock_ghz": 2.4,
             "clock": "nominal",
         },
-        "issue_at_measured_clock": issue_roofline() if (args.ny, args.nx) == (16384, 16384) else None,
+        "issue_at_measured_clock": issue_roofline(args.key_bits) if (args.ny, args.nx) == (16384, 16384) else None,
         "cpu_baseline": cpu,
         "modes_config2": modes,
         "batch_config3": batch3,
