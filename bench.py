@@ -906,13 +906,10 @@ def main():
     payload_gbs = n / (ms_enc * 1e-3) / 1e9
     traffic = 2 * n + aad_len + 16
     blocks = (n + 15) // 16 + (aad_len + 15) // 16 + 1
-    log2B = args.log2_tile
-    if not log2B:
-        # the library chooses the tile size; recover it from the workspace size (a 256-byte counter
-        # block, 16 bytes per tile partial, 16-byte slots for E_K(J0) and J0)
-        tiles = (ctx.workspace_size(n, aad_len) - 256) // 16 - 2
-    else:
-        tiles = -(-blocks // (1 << log2B))
+    # the tile count of the launch the library plans for this message (its partials are written)
+    plan = ctx.launch_plan(len(msg.key), n, aad_len)
+    tiles = plan["tiles"]
+    assert tiles == -(-blocks // (1 << plan["log2_tile_blocks"]))
     tile_bytes = 2 * n + aad_len + 16 * tiles
     nr = len(msg.key) // 4 + 6
     lds_bytes_per_block = 4 * (1 + 4 + 16 * (nr - 3) + 16) + 16 * 16

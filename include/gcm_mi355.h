@@ -137,11 +137,13 @@ int gcm_decrypt_verify_ex(gcm_ctx *ctx, const uint8_t *key, size_t key_len, cons
 
 /* ---------------------------------------------------------------- asynchronous, resident key */
 
-/* Device scratch bytes an asynchronous call on a message of `len` data bytes
- * and `aad_len` AAD bytes needs (the per-tile partial hashes of the map
- * phase, the block E_K(J0) that the reduce phase adds, and J0 itself for IVs
- * other than 96 bits).  A workspace may be
- * reused by calls that are ordered on one stream. */
+/* Device scratch bytes an asynchronous call on a message of up to `len` data
+ * bytes and up to `aad_len` AAD bytes needs (the per-tile partial hashes of
+ * the map phase, the block E_K(J0) that the reduce phase adds, and J0 itself
+ * for IVs other than 96 bits), under the context's current launch settings:
+ * enough for every shorter message as well (the tile count itself is not
+ * monotonic in the length).  A workspace may be reused by calls that are
+ * ordered on one stream. */
 uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
 
 /* Same computation as gcm_encrypt, fully on the device and without host
@@ -346,10 +348,11 @@ int gcm_fits_nonce(uint8_t out[12]);
  * Buffers: device memory, data and AAD 16-byte aligned, input and output
  * identical or disjoint; the tag may sit anywhere in device memory.
  *
- * Device scratch for a message of `len` data and `aad_len` AAD bytes: a key
- * slot for the derived keys (about 403 KiB), the POLYVAL value and counter
- * block, and the per-tile partial hashes.  A workspace may be reused by calls
- * that are ordered on one stream. */
+ * Device scratch for a message of up to `len` data and up to `aad_len` AAD
+ * bytes: a key slot for the derived keys (about 403 KiB), the POLYVAL value
+ * and counter block, and the per-tile partial hashes (enough for every
+ * shorter message too, as for gcm_workspace_size).  A workspace may be
+ * reused by calls that are ordered on one stream. */
 uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
 
 /* Encrypt: ct_d = the ciphertext, tag_d (device, 16 bytes) = the tag, both
@@ -504,7 +507,7 @@ int gcm_set_launch(gcm_ctx *ctx, uint32_t log2_tile_blocks, uint32_t waves_per_g
  * (the autotune cache, else 2).  Results never depend on it. */
 int gcm_set_combine(gcm_ctx *ctx, uint32_t fanin);
 
-/* Result of an autotune search. */
+/* Result of an autotune search (also the answer of gcm_launch_plan). */
 typedef struct gcm_tune_result {
     uint32_t log2_tile_blocks; /* chosen blocks per wave tile (log2); for a batch, the cap on its tiles */
     uint32_t waves_per_group;  /* chosen workgroup size in waves */
@@ -539,6 +542,15 @@ int gcm_autotune(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint32_t reps, gc
  * Blocks until done. */
 int gcm_batch_autotune(gcm_ctx *ctx, const gcm_job *jobs, uint32_t n, uint8_t *base_d, uint64_t base_bytes,
                        uint32_t reps, gcm_tune_result *out, void *stream);
+
+/* The launch an asynchronous single-message call on a message of `len` data
+ * bytes and `aad_len` AAD bytes under a `key_len`-byte key would use now
+ * (explicit settings, else the autotune cache, else the heuristics):
+ * log2_tile_blocks, waves_per_group, groups_per_cu and combine_fanin are
+ * filled, candidates = its number of wave tiles (the message's GHASH blocks
+ * over the tile size, rounded up), best_ms and gbs = 0.  Host only; for
+ * introspection and for figures that need the tile count. */
+int gcm_launch_plan(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint64_t aad_len, gcm_tune_result *out);
 
 /* Persist / restore both autotune caches as JSON (restoring rejects a cache
  * written on another GPU architecture). */

@@ -229,6 +229,26 @@ extern "C" int gcm_set_combine(gcm_ctx *ctx, uint32_t fanin)
     GCM_ABI_CATCH
 }
 
+extern "C" int gcm_launch_plan(gcm_ctx *ctx, uint32_t key_len, uint64_t len, uint64_t aad_len, gcm_tune_result *out)
+{
+    GCM_ABI_TRY
+        if (!ctx || !out)
+            return fail(GCM_E_ARG, "gcm_launch_plan: NULL argument");
+        if (key_len != 16 && key_len != 24 && key_len != 32)
+            return fail(GCM_E_KEYLEN, "key length %u is not 16, 24 or 32", key_len);
+        std::lock_guard<std::mutex> g(ctx->mu);
+        const Shape sh = message_shape(ctx, key_len, len, aad_len);
+        const uint64_t m = ghash_blocks(aad_len, len);
+        std::memset(out, 0, sizeof *out);
+        out->log2_tile_blocks = sh.log2B;
+        out->waves_per_group = sh.waves;
+        out->groups_per_cu = sh.gpc;
+        out->combine_fanin = sh.fanin;
+        out->candidates = (uint32_t)((m + (1ull << sh.log2B) - 1) >> sh.log2B);
+        return GCM_OK;
+    GCM_ABI_CATCH
+}
+
 // ---------------------------------------------------------------- keys
 
 int gcm::register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_t *key_lens, uint32_t n,
@@ -358,6 +378,14 @@ uint32_t gcm::groups_per_cu(uint32_t waves)
     static const uint32_t g8 = (uint32_t)max_groups_per_cu(8), g12 = (uint32_t)max_groups_per_cu(12),
                           g16 = (uint32_t)max_groups_per_cu(16);
     return waves == 8 ? g8 : waves == 12 ? g12 : waves == 16 ? g16 : (uint32_t)max_groups_per_cu((int)waves);
+}
+
+uint64_t gcm::resident_bound(const gcm_ctx *ctx)
+{
+    uint64_t r = 0;
+    for (uint32_t w : {8u, 12u, 16u})
+        r = std::max<uint64_t>(r, (uint64_t)ctx->cu_count * (ctx->cfg_gpc ? ctx->cfg_gpc : groups_per_cu(w)) * w);
+    return r;
 }
 
 Shape gcm::message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len)
@@ -507,7 +535,11 @@ extern "C" uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_
         for (uint32_t kb : {16u, 24u, 32u})  // any key size the call may use: the smallest tiles
             best = std::min(best, message_shape(ctx, kb, len, aad_len).log2B);
         const uint64_t T = (m + (1ull << best) - 1) >> best;
-        return workspace_bytes_for(T, 1);
+        // with explicit launch settings the tile size is fixed, so the count
+        // grows with the length; otherwise cover every shorter message too
+        if (ctx->cfg_log2B)
+            return workspace_bytes_for(T, 1);
+        return workspace_bytes_for(tiles_bound_upto(m, T, resident_bound(ctx)), 1);
     GCM_ABI_CATCH_VALUE(0)
 }
 

@@ -129,6 +129,8 @@ int register_keys_locked(gcm_ctx *ctx, const uint8_t *const *keys, const uint32_
 Shape message_shape(const gcm_ctx *ctx, uint32_t key_bytes, uint64_t len, uint64_t aad_len);
 // groups of the tile kernel (`waves` waves each) a compute unit holds
 uint32_t groups_per_cu(uint32_t waves);
+// the most waves the planners may count as resident (any wave count)
+uint64_t resident_bound(const gcm_ctx *ctx);
 // frees the buffers kept for streamed messages (caller holds ctx->mu; no
 // queued work uses them)
 void stream_pool_release(gcm_ctx *ctx);

@@ -164,6 +164,19 @@ inline uint32_t heuristic_waves(uint64_t m, uint64_t cus, Gpc gpc)
     return best_w;
 }
 
+// Tiles that suffice for every message of at most m GHASH blocks planned by
+// the heuristics above (t_own: the m-block message's own tile count): a
+// tile size below 2^8 blocks is only chosen while the tiles fit the
+// resident waves (at most `resident_max` over the wave counts), larger ones
+// give at most ceil(m / 256) tiles.  The tile count is not monotonic in the
+// length (a longer message may take larger tiles), so a workspace sized for
+// the longest message of a set needs this bound, not its own count.
+inline uint64_t tiles_bound_upto(uint64_t m, uint64_t t_own, uint64_t resident_max)
+{
+    const uint64_t small = std::min<uint64_t>((m + 63) / 64, resident_max);
+    return std::max<uint64_t>(t_own, std::max<uint64_t>(small, (m + 255) / 256));
+}
+
 // Tile size of one message inside a batch: about one workgroup item (waves
 // tiles) for small messages, at most 2^cap blocks per tile for large ones,
 // so the persistent workgroups see items of similar cost.  cap: 6..20.

@@ -157,7 +157,10 @@ extern "C" uint64_t gcm_siv_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t 
         std::lock_guard<std::mutex> g(ctx->mu);
         Shape sh;
         const uint64_t T = siv_tiles(ctx, len, aad_len, &sh);
-        return kSivTilesOff + workspace_bytes_for(T, 1);
+        if (ctx->cfg_log2B)
+            return kSivTilesOff + workspace_bytes_for(T, 1);
+        return kSivTilesOff +
+               workspace_bytes_for(tiles_bound_upto(ghash_blocks(aad_len, len), T, resident_bound(ctx)), 1);
     GCM_ABI_CATCH_VALUE(0)
 }
 

@@ -148,6 +148,7 @@ def load() -> ctypes.CDLL:
         "gcm_autotune": ([vp, u32, u64, u32, vp, vp], ctypes.c_int),
         "gcm_batch_autotune": ([vp, vp, u32, vp, u64, u32, vp, vp], ctypes.c_int),
         "gcm_set_combine": ([vp, u32], ctypes.c_int),
+        "gcm_launch_plan": ([vp, u32, u64, u64, ctypes.POINTER(TuneResult)], ctypes.c_int),
         "gcm_autotune_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_autotune_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         "gcm_profile_enable": ([vp, ctypes.c_int], ctypes.c_int),
@@ -485,6 +486,15 @@ class Context:
 
     def set_combine(self, fanin: int = 0) -> None:
         _check(load().gcm_set_combine(self._h, fanin))
+
+    def launch_plan(self, key_len: int, length: int, aad_len: int = 0) -> dict:
+        """The launch an asynchronous call would use for such a message (see
+        gcm_launch_plan): log2_tile_blocks, waves_per_group, groups_per_cu,
+        combine_fanin and `tiles`."""
+        r = TuneResult()
+        _check(load().gcm_launch_plan(self._h, key_len, length, aad_len, ctypes.byref(r)))
+        return {"log2_tile_blocks": r.log2_tile_blocks, "waves_per_group": r.waves_per_group,
+                "groups_per_cu": r.groups_per_cu, "combine_fanin": r.combine_fanin, "tiles": r.candidates}
 
     def batch_autotune(self, jobs, base, reps: int = 3, stream=None) -> dict:
         """Launch-shape search on a batch (see gcm_batch_autotune); `jobs` and

@@ -283,6 +283,24 @@ int main()
             const uint32_t l = heuristic_log2B(m, cus * w);
             CHECK(busiest_cu_rows(m, l, w, cus, 1) <= busiest_cu_rows(m, l16, 16, cus, 1));
         }
+        // the workspace bound covers every shorter message, whatever wave
+        // count and tile size the planner picks for it
+        for (int it = 0; it < 4000; ++it) {
+            const uint64_t m = 1 + r() % ((1ull << 26) + 1);
+            const uint64_t cus = 1 + r() % 304;
+            const uint32_t lm = heuristic_log2B(m, cus * heuristic_waves(m, cus, gpc1));
+            const uint64_t bound = tiles_bound_upto(m, (m + (1ull << lm) - 1) >> lm, cus * 16);
+            for (int k = 0; k < 8; ++k) {
+                const uint64_t m2 = k == 0 ? m : 1 + r() % m;
+                const uint32_t w = heuristic_waves(m2, cus, gpc1);
+                const uint32_t l = heuristic_log2B(m2, cus * w);
+                CHECK(((m2 + (1ull << l) - 1) >> l) <= bound);
+                for (uint32_t ww : {8u, 12u, 16u}) {  // any explicit wave count
+                    const uint32_t l2 = heuristic_log2B(m2, cus * ww);
+                    CHECK(((m2 + (1ull << l2) - 1) >> l2) <= bound);
+                }
+            }
+        }
         // the measured cases on 256 compute units (AES-256, 2880-byte AAD: 180 blocks)
         CHECK(heuristic_waves((1ull << 16) + 181, 256, gpc1) == 8);   // 1 MiB
         CHECK(heuristic_waves((2ull << 16) + 181, 256, gpc1) == 12);  // 2 MiB

@@ -285,3 +285,71 @@ def test_stream_buffers_reused_across_hip_streams_without_waiting():
     finally:
         torch.cuda.synchronize()
         c.close()
+
+
+def test_streams_from_several_host_threads_share_the_kept_buffers():
+    """Four host threads, each on its own HIP stream, run five streamed
+    messages each on one context: begin / update / final / destroy from the
+    threads interleave on the context's lock and its kept buffers pass from
+    thread to thread (each next user waiting on the previous one's event).
+    Every ciphertext and tag must equal one call of the asynchronous path on
+    the same message (itself checked against the oracle elsewhere)."""
+    import threading
+
+    r = np.random.default_rng(6600)
+    key = r.bytes(32)
+    c = gcm.Context(device=0, key_slots=4)
+    try:
+        slot = c.key_register(key)
+        n_threads, per_thread = 4, 5
+        jobs = []
+        g = torch.Generator(device="cuda")
+        g.manual_seed(6601)
+        for t in range(n_threads):
+            for k in range(per_thread):
+                n = int(r.integers(1, 3 << 20))
+                pt = torch.empty(n, dtype=torch.uint8, device="cuda").random_(0, 256, generator=g)
+                aad = torch.empty(int(r.integers(0, 3000)) // 16 * 16, dtype=torch.uint8,
+                                  device="cuda").random_(0, 256, generator=g)
+                iv = r.bytes(12 if k % 2 == 0 else 20)
+                jobs.append(dict(t=t, pt=pt, aad=aad, iv=iv, ct=torch.empty_like(pt),
+                                 tag=torch.zeros(16, dtype=torch.uint8, device="cuda")))
+        torch.cuda.synchronize()
+        errors = []
+
+        def run(t):
+            s = torch.cuda.Stream()
+            try:
+                for j in [j for j in jobs if j["t"] == t]:
+                    st = c.stream_begin(0, slot, j["iv"], j["aad"] if j["aad"].numel() else None, s)
+                    try:
+                        n = j["pt"].numel()
+                        cut = (n // 3) // 16 * 16
+                        st.update(j["pt"][:cut], j["ct"][:cut], s)
+                        st.update(j["pt"][cut:], j["ct"][cut:], s)
+                        st.final(j["tag"], None, s)
+                    finally:
+                        st.close()
+                s.synchronize()
+            except Exception as e:  # reported by the main thread
+                errors.append(e)
+
+        print(f"threads: {n_threads} x {per_thread} streamed messages", flush=True)
+        threads = [threading.Thread(target=run, args=(t,)) for t in range(n_threads)]
+        for th in threads:
+            th.start()
+        for th in threads:
+            th.join()
+        torch.cuda.synchronize()
+        assert not errors, errors
+        ws = torch.zeros(c.workspace_size(3 << 20, 3000), dtype=torch.uint8, device="cuda")
+        for j in jobs:
+            ct1 = torch.empty_like(j["pt"])
+            tag1 = torch.zeros(16, dtype=torch.uint8, device="cuda")
+            c.encrypt_async(slot, j["iv"], j["aad"] if j["aad"].numel() else None, j["pt"], ct1, tag1, ws)
+            torch.cuda.synchronize()
+            assert torch.equal(j["tag"], tag1), "tag differs from the one-call path"
+            assert torch.equal(j["ct"], ct1), "ciphertext differs from the one-call path"
+    finally:
+        torch.cuda.synchronize()
+        c.close()
