@@ -192,6 +192,78 @@ def test_async_resident_key(ctx):
         ctx.key_release(slot)
 
 
+def test_async_and_oneshot_calls_from_several_host_threads(ctx):
+    """Four host threads on their own HIP streams share one context: two run
+    asynchronous encrypt / decrypt-verify calls with a registered key and their
+    own workspaces, two run one-shot calls (which share the context's own
+    workspace and result block under its lock).  Every result equals the
+    oracle's."""
+    import threading
+
+    r = workloads.rng_for(31)
+    key = workloads.random_bytes(r, 32).tobytes()
+    slot = ctx.key_register(key)
+    cases = []
+    for i in range(16):
+        n = int(r.integers(1, 600_000))
+        cases.append(dict(iv=workloads.random_bytes(r, 12).tobytes(), aad=workloads.random_bytes(r, int(r.integers(0, 300))),
+                          pt=workloads.random_bytes(r, n)))
+    for c in cases:
+        c["rct"], c["rtag"] = oracle.gcm_encrypt(key, c["iv"], c["aad"], c["pt"])
+    errors = []
+
+    def run_async(mine):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                ws = torch.zeros(ctx.workspace_size(600_000, 300), dtype=torch.uint8, device="cuda")
+                for c in mine:
+                    aad_d = to_dev(c["aad"]) if c["aad"].size else None
+                    pt_d = to_dev(c["pt"])
+                    ct_d = torch.empty_like(pt_d)
+                    tag_d = torch.zeros(16, dtype=torch.uint8, device="cuda")
+                    ctx.encrypt_async(slot, c["iv"], aad_d, pt_d, ct_d, tag_d, ws, s)
+                    back = torch.empty_like(ct_d)
+                    acc = torch.full((1,), -1, dtype=torch.int32, device="cuda")
+                    ctx.decrypt_verify_async(slot, c["iv"], aad_d, ct_d, tag_d, back, acc, ws, s)
+                    s.synchronize()
+                    if not (bytes(host(tag_d)) == c["rtag"] and np.array_equal(host(ct_d), c["rct"])
+                            and int(host(acc)[0]) == 1 and np.array_equal(host(back), c["pt"])):
+                        errors.append(f"async case of {c['pt'].size} bytes")
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    def run_oneshot(mine):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for c in mine:
+                    aad_d = to_dev(c["aad"]) if c["aad"].size else None
+                    pt_d = to_dev(c["pt"])
+                    ct_d = torch.empty_like(pt_d)
+                    tag = ctx.encrypt(key, c["iv"], aad_d, pt_d, ct_d, s)
+                    if not (tag == c["rtag"] and np.array_equal(host(ct_d), c["rct"])):
+                        errors.append(f"one-shot case of {c['pt'].size} bytes")
+        except Exception as e:
+            errors.append(e)
+
+    print("threads: 2 asynchronous + 2 one-shot, 4 messages each", flush=True)
+    try:
+        ths = [threading.Thread(target=run_async, args=(cases[0:4],)),
+               threading.Thread(target=run_async, args=(cases[4:8],)),
+               threading.Thread(target=run_oneshot, args=(cases[8:12],)),
+               threading.Thread(target=run_oneshot, args=(cases[12:16],))]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        torch.cuda.synchronize()
+        assert not errors, errors
+    finally:
+        torch.cuda.synchronize()
+        ctx.key_release(slot)
+
+
 def test_empty_inputs(ctx):
     r = workloads.rng_for(31)
     key, iv = workloads.random_bytes(r, 16).tobytes(), workloads.random_bytes(r, 12).tobytes()
