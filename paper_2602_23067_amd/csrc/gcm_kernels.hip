@@ -1072,16 +1072,20 @@ __device__ void wave_tile(const MsgDesc &d, uint64_t t, const uint8_t *__restric
             cur = ctr_round2(h, c, rk, te);
             hc = h;
         }
+        const uint32_t ctr = base + (uint32_t)lane;
         Ctr2 q = cur;
         if ((base & 255u) > 192u) {
             const uint32_t h1 = (h + 1u) & 0xffffffu;
             const Ctr2 nxt = ctr_round2(h1, c, rk, te);
-            const bool up = (base & 255u) + (uint32_t)lane > 255u;
+            // this lane's low counter byte wrapped inside the row; compared in
+            // the top byte, as aes_ctr2 uses it, so that no per-lane constant
+            // stays live across the loop
+            const bool up = (ctr << 24) < (base << 24);
             q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
             cur = nxt;
             hc = h1;
         }
-        const u32x4 ks = aes_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
+        const u32x4 ks = aes_ctr2<NR>(ctr, q, c, rk, lds, lk);
         const u32x4 o = x ^ ks;
         __builtin_nontemporal_store(o, reinterpret_cast<GLOBAL_AS u32x4 *>(dst + loff));
         if (GH)
@@ -1786,16 +1790,17 @@ __device__ void wave_tile_siv(const MsgDesc &d, uint64_t t, const uint8_t *__res
                     cur = siv_round2(h, c, rk, te);
                     hc = h;
                 }
+                const uint32_t ctr = base + (uint32_t)lane;
                 Ctr2 q = cur;
                 if ((base & 255u) > 192u) {
                     const uint32_t h1 = (h + 1u) & 0xffffffu;
                     const Ctr2 nxt = siv_round2(h1, c, rk, te);
-                    const bool up = (base & 255u) + (uint32_t)lane > 255u;
+                    const bool up = (ctr << 24) < (base << 24);  // low counter byte wrapped in the row
                     q = Ctr2{up ? nxt.v0 : cur.v0, up ? nxt.v1 : cur.v1, up ? nxt.v2 : cur.v2, up ? nxt.v3 : cur.v3};
                     cur = nxt;
                     hc = h1;
                 }
-                const u32x4 o = x ^ aes_siv_ctr2<NR>(base + (uint32_t)lane, q, c, rk, lds, lk);
+                const u32x4 o = x ^ aes_siv_ctr2<NR>(ctr, q, c, rk, lds, lk);
                 __builtin_nontemporal_store(
                     o, reinterpret_cast<GLOBAL_AS u32x4 *>(reinterpret_cast<GLOBAL_AS uint8_t *>(out_g + j0) + loff));
                 if (GH)
