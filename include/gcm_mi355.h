@@ -149,7 +149,11 @@ uint64_t gcm_workspace_size(gcm_ctx *ctx, uint64_t len, uint64_t aad_len);
 /* Same computation as gcm_encrypt, fully on the device and without host
  * synchronisation: the key comes from a registered slot, the tag is written
  * to tag_d (device, 16 bytes).  workspace_d: device scratch of at least
- * gcm_workspace_size() bytes, 16-byte aligned. */
+ * gcm_workspace_size() bytes, 16-byte aligned.  The call enqueues kernels
+ * only (no allocation, copy, memset or host wait), so it and
+ * gcm_decrypt_verify_async may be captured into a HIP graph once the kernels
+ * have been launched eagerly (their code is loaded on first use); a replay
+ * reads the buffers' contents at replay time. */
 int gcm_encrypt_async(gcm_ctx *ctx, uint32_t slot, const uint8_t *iv, size_t iv_len, const uint8_t *aad_d,
                       uint64_t aad_len, const uint8_t *pt_d, uint64_t len, uint8_t *ct_d, uint8_t *tag_d,
                       void *workspace_d, uint64_t workspace_bytes, void *stream);
