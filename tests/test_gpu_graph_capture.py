@@ -1,4 +1,5 @@
-"""The resident-key asynchronous calls captured into a HIP graph.
+"""The resident-key asynchronous calls (and the allocation-free one) captured
+into a HIP graph.
 
 gcm_encrypt_async and gcm_decrypt_verify_async with a 96-bit IV enqueue
 kernels only (no allocation, copy, memset or host wait), so a caller may
@@ -95,6 +96,44 @@ def test_captured_async_calls_replay_like_eager(ctx):
             e_ct, e_tag, e_back, e_ok = eager()
             assert np.array_equal(e_ct, g_ct) and e_tag == g_tag
             assert e_ok == g_ok and np.array_equal(e_back, g_back)
+    finally:
+        torch.cuda.synchronize()
+        ctx.key_release(slot)
+
+
+def test_captured_allocation_free_call_replays_like_the_oracle(ctx):
+    """The allocation-free entry point (the library's own fixed scratch) in a
+    graph: two replays over different plaintexts, each equal to the oracle."""
+    r = workloads.rng_for(4343)
+    key = workloads.random_bytes(r, 16).tobytes()
+    iv = workloads.random_bytes(r, 12).tobytes()
+    n, na = (1 << 20) + 33, 100
+    aad_h = workloads.random_bytes(r, na)
+    dev = torch.device("cuda:0")
+    aad = torch.from_numpy(aad_h.copy()).to(dev)
+    pt = torch.zeros(n, dtype=torch.uint8, device=dev)
+    ct = torch.empty(n, dtype=torch.uint8, device=dev)
+    tag = torch.zeros(16, dtype=torch.uint8, device=dev)
+    side = torch.cuda.Stream()
+    slot = ctx.key_register(key, side)
+    side.synchronize()
+    try:
+        ctx.encrypt_async_noalloc(slot, iv, aad, pt, ct, tag, torch.cuda.current_stream())  # warm-up
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=side):
+            ctx.encrypt_async_noalloc(slot, iv, aad, pt, ct, tag, side)
+        torch.cuda.synchronize()
+        for rep in range(2):
+            pt_h = workloads.random_bytes(r, n)
+            pt.copy_(torch.from_numpy(pt_h))
+            torch.cuda.synchronize()
+            print(f"allocation-free replay {rep}: len={n}", flush=True)
+            g.replay()
+            torch.cuda.synchronize()
+            rct, rtag = oracle.gcm_encrypt(key, iv, aad_h, pt_h)
+            assert np.array_equal(ct.cpu().numpy(), rct), f"replay {rep}: ciphertext differs from the oracle"
+            assert bytes(tag.cpu().numpy()) == rtag, f"replay {rep}: tag differs from the oracle"
     finally:
         torch.cuda.synchronize()
         ctx.key_release(slot)
