@@ -435,8 +435,9 @@ __global__ __launch_bounds__(64) void k_key_setup(KeyChunk chunk, const uint32_t
 }
 
 // Fixed-multiplier tables.  Block b < kTab4Levels builds the nibble-position
-// table of H^(2^b); the last block builds the byte-position table of
-// H^(2^kStrideLevel) = H^64, the per-lane Horner multiplier of the tile kernel.
+// table of H^(2^b); the next sixteen build the byte-position table of
+// H^(2^kStrideLevel) = H^64, the per-lane Horner multiplier of the tile
+// kernel, one byte position each.
 // a * b for one operand pair, all 64 lanes of the wave cooperating: lane i
 // contributes the terms of bits i and i+64 of a (b * x^i, b * x^(i+64)), then
 // an XOR across the wave sums them.  Every lane returns the product.
@@ -466,9 +467,12 @@ __device__ u32x4 gf_mul_wave(u32x4 a, u32x4 b)
 
 // Fixed-multiplier tables of one key (grid.y indexes the key).
 //   blocks 0..39:   nibble-position table of H^(2^b)      (fix-ups, combine tree)
-//   block 40:       byte-position table of H^64           (per-lane Horner multiplier)
-//   blocks 41..104: H^e, e = 0..63, and its 4-bit window table for the lane
+//   blocks 40..55:  byte-position table of H^64, position b - 40
+//                   (per-lane Horner multiplier; one block per position, so
+//                   that this table is not the launch's longest block)
+//   blocks 56..119: H^e, e = 0..63, and its 4-bit window table for the lane
 //                   l = 63 - e that multiplies by it in the tile fix-up
+constexpr int kTab8Blocks = 16;
 __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
 {
     __shared__ u32x4 basis[128];  // basis[i] = M * x^i, memory order
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
     const KeySlotHdr *hd = reinterpret_cast<const KeySlotHdr *>(slot);
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
-    if (b <= kTab4Levels) {
+    if (b < kTab4Levels + kTab8Blocks) {
         if (tid == 0) {
             const int lvl = b < kTab4Levels ? b : kStrideLevel;
             m_sh = u32x4{hd->hpow[lvl][0], hd->hpow[lvl][1], hd->hpow[lvl][2], hd->hpow[lvl][3]};
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
         // H^e as the product of H^(2^k) over the set bits of e (one wave),
         // then thread v < 16 writes (v * H^e) mod P for lane 63 - e
         if (tid < 64) {
-            const int e = b - kTab4Levels - 1;
+            const int e = b - kTab4Levels - kTab8Blocks;
             u32x4 m = {0x80u, 0u, 0u, 0u};  // the field's one
             for (int k = 0; k < 6; ++k)
                 if ((e >> k) & 1)
@@ -515,17 +519,16 @@ __global__ __launch_bounds__(256) void k_key_tables(SlotChunk chunk)
         basis[tid] = poly_to_mem(poly_mul_xi(mem_to_poly(mm), tid));
     }
     lds_barrier();
-    if (b == kTab4Levels) {
+    if (b >= kTab4Levels) {
+        // byte position k = b - kTab4Levels, value v = tid; entry-major:
+        // (byte value v at position k) * M at index 16*v + k
         u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab8Off);
-        // entry-major: (byte value v at position k) * M at index 16*v + k
-        for (int e = tid; e < 4096; e += 256) {
-            const int k = e >> 8, v = e & 255;
-            u32x4 acc = {0, 0, 0, 0};
-            for (int t = 0; t < 8; ++t)
-                if ((v >> t) & 1)
-                    acc ^= basis[8 * k + 7 - t];
-            tab[16 * v + k] = acc;
-        }
+        const int k = b - kTab4Levels, v = tid;
+        u32x4 acc = {0, 0, 0, 0};
+        for (int t = 0; t < 8; ++t)
+            if ((v >> t) & 1)
+                acc ^= basis[8 * k + 7 - t];
+        tab[16 * v + k] = acc;
         return;
     }
     u32x4 *tab = reinterpret_cast<u32x4 *>(slot + kSlotTab4Off + (uint64_t)b * kTab4Bytes);
@@ -1887,7 +1890,7 @@ hipError_t launch_key_setup(const uint8_t *const *keys, const uint32_t *key_lens
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLanePows, m), dim3(256), 0, s, sc);
+        hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + kTab8Blocks + kLanePows, m), dim3(256), 0, s, sc);
         e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -2028,7 +2031,7 @@ hipError_t launch_siv_derive(uint64_t kgk_slot, const uint8_t nonce[12], uint64_
         return e;
     SlotChunk sc{};
     sc.slots[0] = out_slot;
-    hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + 1 + kLanePows, 1), dim3(256), 0, s, sc);
+    hipLaunchKernelGGL(k_key_tables, dim3(kTab4Levels + kTab8Blocks + kLanePows, 1), dim3(256), 0, s, sc);
     return hipGetLastError();
 }
 
