@@ -1549,27 +1549,34 @@ __global__ __launch_bounds__(64) void k_siv_derive(uint64_t kgk, SivArg na, uint
 {
     __shared__ uint32_t te0[256], sb[256];
     __shared__ uint32_t h_sh[4];
+    __shared__ uint32_t half_sh[12];
     stage_aes_tables64(te0, sb, te0g, sbg);
     lds_barrier();
     KeySlotHdr *hd = reinterpret_cast<KeySlotHdr *>(out);
-    if (threadIdx.x == 0) {
-        const KeySlotHdr *kh = reinterpret_cast<const KeySlotHdr *>(kgk);
-        const bool k128 = kh->nr == 10;
+    const KeySlotHdr *kh = reinterpret_cast<const KeySlotHdr *>(kgk);
+    const bool k128 = kh->nr == 10;
+    const int nblk = k128 ? 4 : 6;
+    // the nblk key-generating blocks are independent: thread i encrypts
+    // block i, thread 0 then expands the message key from their halves
+    if ((int)threadIdx.x < nblk) {
+        const int i = (int)threadIdx.x;
         uint32_t rkw[4 * (kMaxNr + 1)];
-        for (int i = 0; i < 4 * (kMaxNr + 1); ++i)
-            rkw[i] = kh->rk[i];
-        uint32_t half[12];
-        const int nblk = k128 ? 4 : 6;
-        for (int i = 0; i < nblk; ++i) {
-            const uint32_t in[4] = {(uint32_t)i, na.nonce[0], na.nonce[1], na.nonce[2]};
-            uint32_t o[4];
-            if (k128)
-                aes_block<10>(rkw, te0, sb, in, o);
-            else
-                aes_block<14>(rkw, te0, sb, in, o);
-            half[2 * i] = o[0];
-            half[2 * i + 1] = o[1];
-        }
+        for (int j = 0; j < 4 * (kMaxNr + 1); ++j)
+            rkw[j] = kh->rk[j];
+        const uint32_t in[4] = {(uint32_t)i, na.nonce[0], na.nonce[1], na.nonce[2]};
+        uint32_t o[4];
+        if (k128)
+            aes_block<10>(rkw, te0, sb, in, o);
+        else
+            aes_block<14>(rkw, te0, sb, in, o);
+        half_sh[2 * i] = o[0];
+        half_sh[2 * i + 1] = o[1];
+    }
+    lds_barrier();
+    if (threadIdx.x == 0) {
+        uint32_t half[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < 2 * nblk; ++i)
+            half[i] = half_sh[i];
         uint32_t w[4 * (kMaxNr + 1)];
         if (k128)
             expand_key<4>(half + 4, hd, sb, w);
